@@ -1,0 +1,237 @@
+/*
+ * famsa_lcs.h -- all-pairs LCS similarity stage of FAMSA on gfx950 (MI355X).
+ *
+ * FAMSA (Deorowicz, Debudaj-Grabysz, Gudys; arXiv 1603.06958) measures the
+ * similarity of every pair of sequences in a family by the length of a
+ * longest common subsequence, computed bit-parallel (Methods, "Pairwise
+ * similarities calculation"), and feeds the similarities, as they are
+ * produced, into a single-linkage guide-tree builder that keeps O(k) memory
+ * (Methods, "Determination of the guide tree").  This library computes the
+ * exact int32 LCS length of every pair i < j inside each family on one GPU
+ * and hands the results to the caller as row tiles, so the k x k matrix is
+ * never stored.
+ *
+ * Conventions for every call:
+ *  - Functions return 0 (FAMSA_LCS_OK) or a negative famsa_lcs_status; the
+ *    text of the last error on the calling thread is famsa_lcs_last_error().
+ *    Nothing is reported through errno or exceptions.
+ *  - Argument validation happens before any HIP call, so invalid input is
+ *    rejected with FAMSA_LCS_EINVAL even on a machine without a GPU.
+ *  - Host pointers are read during the call only; the library copies what it
+ *    keeps.  Device and pinned memory the library allocates belongs to the
+ *    object that allocated it and is freed by its release/destroy call.
+ *  - Sequence i of a batch is codes[seq_off[i] .. seq_off[i+1]); codes are
+ *    symbol indices in [0, alphabet_size).  The paper's alphabet has 32
+ *    codes (twenty amino acids plus special symbols; Methods, "Progressive
+ *    construction of the alignment"); two codes match only when equal.
+ *  - Lengths are limited to FAMSA_LCS_MAX_LEN residues; empty sequences are
+ *    allowed and have LCS 0 with everything.
+ */
+#ifndef FAMSA_LCS_H
+#define FAMSA_LCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FAMSA_LCS_ABI_VERSION 1
+#define FAMSA_LCS_MAX_LEN 65535u
+#define FAMSA_LCS_MAX_ALPHABET 32u
+
+typedef enum famsa_lcs_status {
+  FAMSA_LCS_OK = 0,
+  FAMSA_LCS_EINVAL = -1,     /* bad argument; nothing was done */
+  FAMSA_LCS_ENOMEM = -2,     /* host, pinned or device allocation failed, or the HBM budget is too small */
+  FAMSA_LCS_EDEVICE = -3,    /* a HIP call failed (no GPU, fault, ...) */
+  FAMSA_LCS_ECANCELED = -4,  /* a tile callback returned nonzero */
+  FAMSA_LCS_EBUSY = -5       /* object already in use on this or another thread */
+} famsa_lcs_status;
+
+/* Option flags. */
+#define FAMSA_LCS_PLAIN        0x1u  /* baseline: one pair per lane, 64-bit words, masks from global memory,
+                                        one launch per tile, no work queue, no autotune, no graph */
+#define FAMSA_LCS_DESCENDING   0x2u  /* deliver each family's row tiles from the last to the first */
+#define FAMSA_LCS_DEVICE_TILES 0x4u  /* deliver device pointers (no copy to host); valid during the callback,
+                                        whose GPU work must be ordered on famsa_lcs_tile.stream */
+#define FAMSA_LCS_NO_GRAPH     0x8u  /* launch kernels directly instead of replaying a captured hipGraph */
+#define FAMSA_LCS_NO_AUTOTUNE  0x10u /* use the built-in launch parameters; ignore the tuning cache */
+
+typedef struct famsa_lcs_options {
+  uint32_t struct_size;    /* sizeof(famsa_lcs_options) as the caller compiled it */
+  uint32_t alphabet_size;  /* 1..32; every code must be below it (default 20) */
+  uint32_t tile_rows;      /* rows per tile, >= 1 (default 1024) */
+  int32_t device;          /* HIP device ordinal (default 0) */
+  void* stream;            /* hipStream_t the caller orders its own work on, or NULL (library stream) */
+  uint64_t hbm_budget;     /* device bytes the plan may hold; 0 = 90% of free memory at plan time */
+  uint32_t flags;          /* FAMSA_LCS_* flags above */
+  uint32_t cols_per_item;  /* columns per work item, 0 = tuned/default */
+  uint64_t step_values;    /* int32 values per launch step (several tiles), 0 = default (2^27) */
+} famsa_lcs_options;
+
+/* Fill *opt with the defaults above. */
+void famsa_lcs_default_options(famsa_lcs_options* opt);
+
+/* Opaque handles, owned by the library.  (The call that makes a plan is
+ * famsa_lcs_plan, so the type carries a _t suffix.) */
+typedef struct famsa_lcs_plan_s famsa_lcs_plan_t;
+
+/*
+ * Validate the batch, copy it to the device, build the per-symbol match
+ * bit masks and the work lists, allocate tile buffers, and return a plan.
+ *   codes      nseq sequences back to back (may be NULL if all are empty)
+ *   seq_off    nseq + 1 non-decreasing offsets into codes
+ *   fam_off    nfam + 1 non-decreasing offsets into the sequence list with
+ *              fam_off[0] = 0 and fam_off[nfam] = nseq; NULL means one
+ *              family of all nseq sequences (then nfam is ignored)
+ *   opt        options, or NULL for the defaults
+ *   out        receives the plan; set to NULL on failure
+ * Errors: EINVAL (bad offsets, code >= alphabet_size, length over
+ * FAMSA_LCS_MAX_LEN, bad options), ENOMEM (budget or allocation), EDEVICE.
+ */
+int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
+                    const uint32_t* fam_off, uint32_t nfam, const famsa_lcs_options* opt,
+                    famsa_lcs_plan_t** out);
+
+/* One row tile: rows [row_begin, row_end) of family `family`; row i holds
+ * LCS(i, j) for j = i+1 .. k-1 (family-local indices, the caller's order),
+ * rows back to back, `count` int32 values in total. */
+typedef struct famsa_lcs_tile {
+  uint64_t tile_index;   /* position in the plan's delivery order (resume point) */
+  uint32_t family;       /* family id (serving: job id) */
+  uint32_t k;            /* family size */
+  uint32_t row_begin, row_end;
+  const int32_t* lcs;    /* host memory, or device memory under FAMSA_LCS_DEVICE_TILES */
+  uint64_t count;
+  void* stream;          /* hipStream_t the tile was produced on */
+} famsa_lcs_tile;
+
+/* Tile consumer; return 0 to continue, nonzero to cancel. */
+typedef int (*famsa_lcs_tile_fn)(void* user, const famsa_lcs_tile* tile);
+
+/*
+ * Compute and deliver every tile with index >= first_tile, in order, calling
+ * fn(user, tile) on the calling thread.  The tile memory is valid only during
+ * the callback.  While a callback runs, the next tiles are being computed.
+ * Errors: EINVAL (NULL plan/fn, first_tile > tile count), EBUSY (plan in
+ * use, e.g. called from inside its own callback), ECANCELED, EDEVICE.
+ * After any error the plan is still valid and can be run again.
+ */
+int famsa_lcs_tiles(famsa_lcs_plan_t* plan, uint64_t first_tile, famsa_lcs_tile_fn fn, void* user);
+
+/* Free everything the plan holds.  NULL is a no-op. */
+void famsa_lcs_release(famsa_lcs_plan_t* plan);
+
+/* Thread-local text of the last error ("" if none). */
+const char* famsa_lcs_last_error(void);
+
+typedef struct famsa_lcs_plan_info {
+  uint64_t ntiles;         /* tiles delivered by a full famsa_lcs_tiles call */
+  uint64_t nsteps;         /* launch steps (each one kernel launch per length class) */
+  uint64_t pairs;          /* sum over families of k(k-1)/2 */
+  uint64_t cells;          /* sum over pairs of |A||B| */
+  uint64_t device_bytes;   /* device memory the plan holds */
+  uint64_t pinned_bytes;   /* pinned host memory the plan holds */
+  uint64_t max_tile_values;
+  uint32_t nfam, max_len;
+  uint32_t cols_per_item;  /* launch parameters in force */
+  uint32_t waves_per_group[4];
+} famsa_lcs_plan_info;
+
+int famsa_lcs_plan_get_info(const famsa_lcs_plan_t* plan, famsa_lcs_plan_info* info);
+
+/* Dry run: the same validation and host-side planning as famsa_lcs_plan
+ * (tiles, launch steps, per-step work lists for the kernels) with no HIP
+ * call at all, for inspecting a decomposition on any machine.  Device
+ * fields of *info (device_bytes, pinned_bytes, waves) are 0.  If dump_path
+ * is not NULL the work lists are written there (binary: the magic
+ * "FLCSDMP1", then for each array a uint64 count, a uint64 element size and
+ * the elements: tiles, steps, step ranges, groups, lanes, items, plain rows,
+ * column map, row bases, sequence lengths, family offsets).
+ * Errors: EINVAL as for famsa_lcs_plan, or when the file cannot be written. */
+int famsa_lcs_plan_dry_run(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, const uint32_t* fam_off,
+                           uint32_t nfam, const famsa_lcs_options* opt, const char* dump_path,
+                           famsa_lcs_plan_info* info);
+
+/* Timing of the last famsa_lcs_tiles call, from HIP events on the compute
+ * streams.  Per-kernel times are recorded only for plans that launch without
+ * a graph (FAMSA_LCS_NO_GRAPH or FAMSA_LCS_PLAIN); step_ms is always there. */
+typedef struct famsa_lcs_stats {
+  double kernel_ms[4];     /* summed duration per kernel: [0] rows <= 256 residues, [1] <= 512, [2] <= 1024,
+                              [3] plain one-pair-per-lane kernel (baseline, and rows too long for the others) */
+  uint64_t launches[4];
+  uint64_t cells[4];       /* algorithmic cells |A||B| assigned to each kernel over the whole plan */
+  double step_ms;          /* summed device time of the launch steps (all kernels of a step) */
+  uint64_t steps;
+  double wall_ms;          /* first launch to last callback return */
+  uint64_t tiles;
+} famsa_lcs_stats;
+
+int famsa_lcs_get_stats(const famsa_lcs_plan_t* plan, famsa_lcs_stats* stats);
+
+/* ------------------------------------------------------------------------
+ * Single-linkage consumer (Methods, "Determination of the guide tree": the
+ * tree is built incrementally by SLINK in O(k^2) time and O(k) memory, fed
+ * while the similarities are produced).  Similarity is LCS / indel^2 with
+ * indel = |A| + |B| - 2 LCS (the two equations of "Pairwise similarities
+ * calculation"); indel = 0 (identical sequences) counts as +infinity.
+ * Points are inserted from k-1 down to 0, so the consumer needs the tiles of
+ * one family in descending order (FAMSA_LCS_DESCENDING); it keeps the
+ * pointer representation pi(i) (the later point i joins) and lambda(i) (the
+ * similarity at which it joins) as exact rationals L/indel^2, compared by
+ * 64-bit cross-multiplication (exact for lengths up to FAMSA_LCS_MAX_LEN).
+ * ------------------------------------------------------------------------ */
+typedef struct famsa_slink_s famsa_slink_t;
+
+/* lengths: k sequence lengths of the family (copied). */
+int famsa_slink_create(const uint32_t* lengths, uint32_t k, famsa_slink_t** out);
+/* A famsa_lcs_tile_fn: pass the famsa_slink_t* as `user`.  Host tiles only.
+ * Returns nonzero (cancel) if tiles arrive out of order. */
+int famsa_slink_consume(void* slink, const famsa_lcs_tile* tile);
+/* After all rows are in, by original index i: pi[i] (the root, index 0,
+ * points to itself) and lambda[i] = lambda_num[i] / lambda_den[i]; den 0 with
+ * num >= 0 is +infinity (identical sequences), and the root has num -1,
+ * den 0 (never joins).  NULL outputs are skipped.  EINVAL before all rows. */
+int famsa_slink_result(const famsa_slink_t* s, uint32_t* pi, int64_t* lambda_num, int64_t* lambda_den);
+/* Rows inserted so far. */
+uint32_t famsa_slink_rows_done(const famsa_slink_t* s);
+void famsa_slink_destroy(famsa_slink_t* s);
+
+/* ------------------------------------------------------------------------
+ * Serving: similarity jobs (each one family) are admitted while their device
+ * footprint fits the budget, kept resident, and batched together: every
+ * scheduler step gathers the next tiles of all admitted jobs into one launch
+ * per length class, so a job that arrives while others run joins on the next
+ * step.  Results are identical to running each job alone.
+ * ------------------------------------------------------------------------ */
+typedef struct famsa_lcs_server_s famsa_lcs_server_t;
+
+/* opt->hbm_budget bounds the resident jobs plus step buffers (0 = 90% of free). */
+int famsa_lcs_server_create(const famsa_lcs_options* opt, famsa_lcs_server_t** out);
+/* Queue a job (one family); inputs are copied.  *job_id receives its id.
+ * EINVAL as for famsa_lcs_plan_create; ENOMEM if the job alone can never fit. */
+int famsa_lcs_server_submit(famsa_lcs_server_t* srv, const uint8_t* codes, const uint64_t* seq_off,
+                            uint32_t nseq, uint32_t* job_id);
+/* Admit queued jobs that fit, run one step over all admitted jobs, deliver its
+ * tiles (tile.family = job id, per-job tile_index), retire finished jobs.
+ * *active receives the number of jobs still admitted or queued. */
+int famsa_lcs_server_step(famsa_lcs_server_t* srv, famsa_lcs_tile_fn fn, void* user, uint32_t* active);
+/* Job state: 0 queued, 1 admitted, 2 done. */
+int famsa_lcs_server_job_state(const famsa_lcs_server_t* srv, uint32_t job_id, int* state);
+/* Device bytes held now and the high-water mark. */
+int famsa_lcs_server_memory(const famsa_lcs_server_t* srv, uint64_t* in_use, uint64_t* peak);
+void famsa_lcs_server_destroy(famsa_lcs_server_t* srv);
+
+/* ------------------------------------------------------------------------
+ * Autotuning: time candidate launch parameters (waves per group per length
+ * class, columns per work item) on a sample of the plan's work and store the
+ * winner in a JSON cache keyed by GPU architecture and alphabet size
+ * (path: FAMSA_LCS_TUNE_CACHE, else none).  Results never change.
+ * ------------------------------------------------------------------------ */
+int famsa_lcs_autotune(famsa_lcs_plan_t* plan, const char* cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAMSA_LCS_H */

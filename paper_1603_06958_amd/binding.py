@@ -1,0 +1,287 @@
+"""ctypes binding of libfamsa_lcs.so -- argument marshalling only.
+
+Every step of the similarity computation runs in the HIP library; this
+module converts numpy arrays to pointers, wraps Python callables as tile
+callbacks and raises ``FamsaError`` on nonzero status.  It fails loudly when
+the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Callable, Dict, Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfamsa_lcs.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5
+PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE = 0x1, 0x2, 0x4, 0x8, 0x10
+MAX_LEN = 65535
+
+_STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECANCELED: "ECANCELED", EBUSY: "EBUSY"}
+
+
+class FamsaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("alphabet_size", ctypes.c_uint32),
+                ("tile_rows", ctypes.c_uint32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("hbm_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("cols_per_item", ctypes.c_uint32),
+                ("step_values", ctypes.c_uint64)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("tile_index", ctypes.c_uint64), ("family", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("row_begin", ctypes.c_uint32), ("row_end", ctypes.c_uint32),
+                ("lcs", ctypes.POINTER(ctypes.c_int32)), ("count", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("ntiles", ctypes.c_uint64), ("nsteps", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
+                ("cells", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("pinned_bytes", ctypes.c_uint64),
+                ("max_tile_values", ctypes.c_uint64), ("nfam", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
+                ("cols_per_item", ctypes.c_uint32), ("waves_per_group", ctypes.c_uint32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double * 4), ("launches", ctypes.c_uint64 * 4),
+                ("cells", ctypes.c_uint64 * 4), ("step_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
+                ("wall_ms", ctypes.c_double), ("tiles", ctypes.c_uint64)]
+
+
+TILE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(Tile))
+
+_lib = None
+
+
+def lib():
+    """Load libfamsa_lcs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FamsaError(EDEVICE, f"{LIB_PATH} is missing: build it with `python -m paper_1603_06958_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u8p, u32p, u64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint32), \
+            ctypes.POINTER(ctypes.c_uint64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.famsa_lcs_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.famsa_lcs_default_options.restype = None
+        L.famsa_lcs_plan.argtypes = [u8p, u64p, ctypes.c_uint32, u32p, ctypes.c_uint32, ctypes.POINTER(Options),
+                                     ctypes.POINTER(vp)]
+        L.famsa_lcs_plan.restype = ctypes.c_int
+        L.famsa_lcs_tiles.argtypes = [vp, ctypes.c_uint64, TILE_FN, vp]
+        L.famsa_lcs_tiles.restype = ctypes.c_int
+        L.famsa_lcs_release.argtypes = [vp]
+        L.famsa_lcs_release.restype = None
+        L.famsa_lcs_last_error.argtypes = []
+        L.famsa_lcs_last_error.restype = ctypes.c_char_p
+        L.famsa_lcs_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.famsa_lcs_plan_get_info.restype = ctypes.c_int
+        L.famsa_lcs_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.famsa_lcs_get_stats.restype = ctypes.c_int
+        L.famsa_lcs_autotune.argtypes = [vp, ctypes.c_char_p]
+        L.famsa_lcs_autotune.restype = ctypes.c_int
+        L.famsa_slink_create.argtypes = [u32p, ctypes.c_uint32, ctypes.POINTER(vp)]
+        L.famsa_slink_create.restype = ctypes.c_int
+        L.famsa_slink_consume.argtypes = [vp, ctypes.POINTER(Tile)]
+        L.famsa_slink_consume.restype = ctypes.c_int
+        L.famsa_slink_result.argtypes = [vp, u32p, i64p, i64p]
+        L.famsa_slink_result.restype = ctypes.c_int
+        L.famsa_slink_rows_done.argtypes = [vp]
+        L.famsa_slink_rows_done.restype = ctypes.c_uint32
+        L.famsa_slink_destroy.argtypes = [vp]
+        L.famsa_slink_destroy.restype = None
+        L.famsa_lcs_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.famsa_lcs_server_create.restype = ctypes.c_int
+        L.famsa_lcs_server_submit.argtypes = [vp, u8p, u64p, ctypes.c_uint32, u32p]
+        L.famsa_lcs_server_submit.restype = ctypes.c_int
+        L.famsa_lcs_server_step.argtypes = [vp, TILE_FN, vp, u32p]
+        L.famsa_lcs_server_step.restype = ctypes.c_int
+        L.famsa_lcs_server_job_state.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int)]
+        L.famsa_lcs_server_job_state.restype = ctypes.c_int
+        L.famsa_lcs_server_memory.argtypes = [vp, u64p, u64p]
+        L.famsa_lcs_server_memory.restype = ctypes.c_int
+        L.famsa_lcs_server_destroy.argtypes = [vp]
+        L.famsa_lcs_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return (lib().famsa_lcs_last_error() or b"").decode()
+
+
+def check(rc: int):
+    if rc != OK:
+        raise FamsaError(rc, last_error())
+    return rc
+
+
+def make_options(alphabet_size: int = 20, tile_rows: int = 1024, device: int = 0, stream: Optional[int] = None,
+                 hbm_budget: int = 0, flags: int = 0, cols_per_item: int = 0, step_values: int = 0) -> Options:
+    o = Options()
+    lib().famsa_lcs_default_options(ctypes.byref(o))
+    o.alphabet_size = alphabet_size
+    o.tile_rows = tile_rows
+    o.device = device
+    o.stream = stream
+    o.hbm_budget = hbm_budget
+    o.flags = flags
+    o.cols_per_item = cols_per_item
+    o.step_values = step_values
+    return o
+
+
+def torch_stream_handle() -> Optional[int]:
+    """hipStream_t of torch's current stream on the current device (None if torch has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+class Plan:
+    """A famsa_lcs plan over a batch of families (see include/famsa_lcs.h)."""
+
+    def __init__(self, codes: np.ndarray, seq_off: np.ndarray, fam_off: Optional[np.ndarray] = None, **opts):
+        self._codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        self._off = np.ascontiguousarray(seq_off, dtype=np.uint64)
+        self._fam = None if fam_off is None else np.ascontiguousarray(fam_off, dtype=np.uint32)
+        nseq = self._off.size - 1
+        self.options = make_options(**opts)
+        h = ctypes.c_void_p()
+        cp = _ptr(self._codes, ctypes.c_uint8) if self._codes.size else None
+        fp = _ptr(self._fam, ctypes.c_uint32) if self._fam is not None else None
+        nfam = 0 if self._fam is None else self._fam.size - 1
+        check(lib().famsa_lcs_plan(cp, _ptr(self._off, ctypes.c_uint64), nseq, fp, nfam,
+                                   ctypes.byref(self.options), ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_batch(cls, b, **opts) -> "Plan":
+        return cls(b.codes, b.seq_off, b.fam_off, **opts)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().famsa_lcs_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self) -> PlanInfo:
+        i = PlanInfo()
+        check(lib().famsa_lcs_plan_get_info(self.handle, ctypes.byref(i)))
+        return i
+
+    def stats(self) -> Stats:
+        s = Stats()
+        check(lib().famsa_lcs_get_stats(self.handle, ctypes.byref(s)))
+        return s
+
+    def run(self, fn: Callable[[Tile], int], first_tile: int = 0) -> int:
+        """Deliver tiles to fn(tile) (a ctypes Tile); fn returns 0 to continue."""
+        err = []
+
+        def cb(_user, tp):
+            try:
+                return int(fn(tp.contents) or 0)
+            except BaseException as e:  # never let an exception cross the C frame
+                err.append(e)
+                return 1
+
+        c = TILE_FN(cb)
+        rc = lib().famsa_lcs_tiles(self.handle, first_tile, c, None)
+        if err:
+            raise err[0]
+        return check(rc)
+
+    def run_native(self, fn_ptr, user, first_tile: int = 0) -> int:
+        """Deliver tiles to a C callback (e.g. famsa_slink_consume)."""
+        return check(lib().famsa_lcs_tiles(self.handle, first_tile, fn_ptr, user))
+
+    def collect(self, first_tile: int = 0) -> Dict[Tuple[int, int, int], np.ndarray]:
+        """All host tiles as {(family, row_begin, row_end): int32 array copy}."""
+        out = {}
+
+        def fn(t: Tile):
+            arr = np.ctypeslib.as_array(t.lcs, shape=(t.count,)).copy() if t.count else np.zeros(0, np.int32)
+            out[(t.family, t.row_begin, t.row_end)] = arr
+            return 0
+
+        self.run(fn, first_tile)
+        return out
+
+    def autotune(self, cache_path: Optional[str] = None) -> int:
+        return check(lib().famsa_lcs_autotune(self.handle, cache_path.encode() if cache_path else None))
+
+
+def tile_array(t: Tile) -> np.ndarray:
+    """View of a host tile's values (valid during the callback only)."""
+    if t.count == 0:
+        return np.zeros(0, np.int32)
+    return np.ctypeslib.as_array(t.lcs, shape=(t.count,))
+
+
+class SLink:
+    """Host single-linkage consumer (famsa_slink_*)."""
+
+    def __init__(self, lengths: np.ndarray):
+        self._len = np.ascontiguousarray(lengths, dtype=np.uint32)
+        h = ctypes.c_void_p()
+        check(lib().famsa_slink_create(_ptr(self._len, ctypes.c_uint32) if self._len.size else None,
+                                       self._len.size, ctypes.byref(h)))
+        self.handle = h
+        self.k = int(self._len.size)
+
+    # the C function pointer to hand to Plan.run_native
+    @staticmethod
+    def consume_fn():
+        return ctypes.cast(lib().famsa_slink_consume, TILE_FN)
+
+    def feed(self, t: Tile) -> int:
+        return lib().famsa_slink_consume(self.handle, ctypes.byref(t))
+
+    def rows_done(self) -> int:
+        return int(lib().famsa_slink_rows_done(self.handle))
+
+    def result(self):
+        pi = np.zeros(self.k, np.uint32)
+        num = np.zeros(self.k, np.int64)
+        den = np.zeros(self.k, np.int64)
+        check(lib().famsa_slink_result(self.handle, _ptr(pi, ctypes.c_uint32), _ptr(num, ctypes.c_int64),
+                                       _ptr(den, ctypes.c_int64)))
+        return pi, num, den
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().famsa_slink_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,414 @@
+// Host runtime pieces shared by plans and the serving loop: errors, memory,
+// validation, the device batch with its masks, and the work decomposition.
+#include "runtime.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+
+namespace famsa {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error_text() { return g_err.c_str(); }
+
+void DevMem::reset() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+int DevMem::alloc(size_t n) {
+  reset();
+  if (n == 0) n = 16;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return set_error(e == hipErrorOutOfMemory ? FAMSA_LCS_ENOMEM : FAMSA_LCS_EDEVICE, "hipMalloc(%zu): %s", n,
+                     hipGetErrorString(e));
+  }
+  bytes = n;
+  return 0;
+}
+
+void PinMem::reset() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+int PinMem::alloc(size_t n) {
+  reset();
+  if (n == 0) n = 16;
+  hipError_t e = hipHostMalloc(&p, n, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return set_error(FAMSA_LCS_ENOMEM, "hipHostMalloc(%zu): %s", n, hipGetErrorString(e));
+  }
+  bytes = n;
+  return 0;
+}
+
+int normalize_options(const famsa_lcs_options* in, Opts* o) {
+  famsa_lcs_options d;
+  famsa_lcs_default_options(&d);
+  if (in) {
+    if (in->struct_size < offsetof(famsa_lcs_options, cols_per_item))
+      return set_error(FAMSA_LCS_EINVAL, "options.struct_size %u is too small", in->struct_size);
+    const size_t n = std::min<size_t>(in->struct_size, sizeof d);
+    memcpy(&d, in, n);
+    d.struct_size = sizeof d;
+  }
+  if (d.alphabet_size < 1 || d.alphabet_size > FAMSA_LCS_MAX_ALPHABET)
+    return set_error(FAMSA_LCS_EINVAL, "alphabet_size %u not in [1, %u]", d.alphabet_size, FAMSA_LCS_MAX_ALPHABET);
+  if (d.tile_rows < 1) return set_error(FAMSA_LCS_EINVAL, "tile_rows must be >= 1");
+  if (d.device < 0) return set_error(FAMSA_LCS_EINVAL, "device %d < 0", d.device);
+  const uint32_t known = FAMSA_LCS_PLAIN | FAMSA_LCS_DESCENDING | FAMSA_LCS_DEVICE_TILES | FAMSA_LCS_NO_GRAPH |
+                         FAMSA_LCS_NO_AUTOTUNE;
+  if (d.flags & ~known) return set_error(FAMSA_LCS_EINVAL, "unknown flag bits 0x%x", d.flags & ~known);
+  if (d.cols_per_item > (1u << 20)) return set_error(FAMSA_LCS_EINVAL, "cols_per_item %u too large", d.cols_per_item);
+  o->sigma = d.alphabet_size;
+  o->tile_rows = d.tile_rows;
+  o->device = d.device;
+  o->user_stream = (hipStream_t)d.stream;
+  o->hbm_budget = d.hbm_budget;
+  o->flags = d.flags;
+  o->cols_per_item = d.cols_per_item;
+  o->step_values = d.step_values ? d.step_values : (1ull << 27);
+  return 0;
+}
+
+int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, const uint32_t* fam_off,
+                   uint32_t nfam, uint32_t sigma, std::vector<uint32_t>* fam_out, uint32_t* max_len) {
+  if (!seq_off) return set_error(FAMSA_LCS_EINVAL, "seq_off is NULL");
+  if (nseq >= 0xFFFFFFF0u) return set_error(FAMSA_LCS_EINVAL, "nseq %u too large", nseq);
+  uint32_t mx = 0;
+  for (uint32_t i = 0; i < nseq; ++i) {
+    if (seq_off[i + 1] < seq_off[i])
+      return set_error(FAMSA_LCS_EINVAL, "seq_off decreases at %u (%llu > %llu)", i,
+                       (unsigned long long)seq_off[i], (unsigned long long)seq_off[i + 1]);
+    const uint64_t L = seq_off[i + 1] - seq_off[i];
+    if (L > FAMSA_LCS_MAX_LEN)
+      return set_error(FAMSA_LCS_EINVAL, "sequence %u has length %llu > %u", i, (unsigned long long)L,
+                       FAMSA_LCS_MAX_LEN);
+    mx = std::max<uint32_t>(mx, (uint32_t)L);
+  }
+  const uint64_t lo = nseq ? seq_off[0] : 0, hi = nseq ? seq_off[nseq] : 0;
+  if (hi > lo && !codes) return set_error(FAMSA_LCS_EINVAL, "codes is NULL but %llu residues are given",
+                                          (unsigned long long)(hi - lo));
+  for (uint64_t p = lo; p < hi; ++p)
+    if (codes[p] >= sigma)
+      return set_error(FAMSA_LCS_EINVAL, "code %u at offset %llu is not below alphabet_size %u", codes[p],
+                       (unsigned long long)p, sigma);
+  fam_out->clear();
+  if (!fam_off) {
+    fam_out->push_back(0);
+    fam_out->push_back(nseq);
+  } else {
+    if (nfam == 0 && nseq != 0) return set_error(FAMSA_LCS_EINVAL, "nfam is 0 but nseq is %u", nseq);
+    if (fam_off[0] != 0) return set_error(FAMSA_LCS_EINVAL, "fam_off[0] must be 0");
+    if (fam_off[nfam] != nseq) return set_error(FAMSA_LCS_EINVAL, "fam_off[nfam] = %u != nseq %u", fam_off[nfam], nseq);
+    for (uint32_t f = 0; f < nfam; ++f)
+      if (fam_off[f + 1] < fam_off[f]) return set_error(FAMSA_LCS_EINVAL, "fam_off decreases at %u", f);
+    fam_out->assign(fam_off, fam_off + nfam + 1);
+  }
+  *max_len = mx;
+  return 0;
+}
+
+DeviceBatch DeviceBatchOwner::view() const {
+  return DeviceBatch{codes.as<uint8_t>(), dev_off.as<uint64_t>(), len.as<uint32_t>(), mask_off.as<uint64_t>(),
+                     masks.as<uint32_t>()};
+}
+
+static inline uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+uint64_t DeviceBatchOwner::footprint(const uint64_t* seq_off, uint32_t nseq, uint32_t sigma) {
+  uint64_t cb = 0, words = 0;
+  for (uint32_t i = 0; i < nseq; ++i) {
+    const uint64_t L = seq_off[i + 1] - seq_off[i];
+    cb += round_up(L, kSeqAlign);
+    words += (L + 31) / 32;
+  }
+  return cb + 32 + (uint64_t)nseq * (8 + 4 + 8 + 8) + 16 + words * sigma * 4;
+}
+
+int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uint32_t n, uint32_t sig,
+                             hipStream_t s) {
+  nseq = n;
+  sigma = sig;
+  h_len.resize(n);
+  h_lenprefix.assign(n + 1, 0);
+  std::vector<uint64_t> hoff(n + 1), hmo(n + 1), hwp(n + 1);
+  uint64_t cb = 0, mw = 0, words = 0;
+  max_len = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t L = (uint32_t)(seq_off[i + 1] - seq_off[i]);
+    h_len[i] = L;
+    h_lenprefix[i + 1] = h_lenprefix[i] + L;
+    max_len = std::max(max_len, L);
+    hoff[i] = cb;
+    cb += round_up(L, kSeqAlign);
+    const uint64_t W = (L + 31) / 32;
+    hmo[i] = mw;
+    mw += W * sigma;
+    hwp[i] = words;
+    words += W;
+  }
+  hoff[n] = cb;
+  hmo[n] = mw;
+  hwp[n] = words;
+  std::vector<uint8_t> packed(cb + 32, 0);
+  for (uint32_t i = 0; i < n; ++i)
+    if (h_len[i]) memcpy(packed.data() + hoff[i], hcodes + seq_off[i], h_len[i]);
+  int rc;
+  if ((rc = upload(codes, packed, s))) return rc;
+  if ((rc = upload(dev_off, hoff, s))) return rc;
+  if ((rc = upload(len, h_len, s))) return rc;
+  if ((rc = upload(mask_off, hmo, s))) return rc;
+  if ((rc = upload(wprefix, hwp, s))) return rc;
+  if ((rc = masks.alloc(mw * 4 + 16))) return rc;
+  const DeviceBatch v = view();
+  int e = launch_build_masks(v, wprefix.as<uint64_t>(), n, words, sigma, masks.as<uint32_t>(), s);
+  if (e) return set_error(FAMSA_LCS_EDEVICE, "build_masks launch failed: %s", hipGetErrorString((hipError_t)e));
+  // host staging vectors above are freed on return: wait for the copies
+  FAMSA_HIP(hipStreamSynchronize(s));
+  bytes = codes.bytes + dev_off.bytes + len.bytes + mask_off.bytes + masks.bytes + wprefix.bytes;
+  return 0;
+}
+
+int class_of(uint32_t W, uint32_t sigma) {
+  if (fast_lds_bytes(sigma, W) + kLdsReserve > g_max_lds) return 3;
+  for (int c = 0; c < 3; ++c)
+    if (W <= (uint32_t)kClassWMax[c]) return c;
+  return 3;
+}
+
+namespace {
+struct CostItem {
+  uint64_t cost;
+  ItemDesc it;
+};
+}  // namespace
+
+void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::vector<uint32_t>& len,
+                const std::vector<uint64_t>& lenprefix, uint32_t sigma, const LaunchParams& lp, bool plain_only) {
+  StepRange r{};
+  std::vector<CostItem> ci[3];
+  std::vector<PlainRow> pr;
+  uint64_t plain_pairs = 0;
+
+  struct PendingGroup {
+    GroupDesc g;
+    uint32_t c0, c1;          // column positions
+    const uint64_t* colpref;  // prefix sums of column lengths by position (family mode), or NULL
+    uint64_t fam_pref0;       // lenprefix base (tile mode)
+  };
+  std::vector<PendingGroup> pend;
+  std::vector<std::vector<uint64_t>> colprefs;
+  colprefs.reserve(fams.size());
+  uint64_t span = 0;
+
+  auto add_plain = [&](const LaneDesc& ld, uint32_t fb, uint32_t ncols, uint32_t cm, uint32_t rb) {
+    if (ld.pos + 1 >= ncols) return;  // no pairs
+    PlainRow p{};
+    p.out_off = ld.out_off;
+    p.pair_first = plain_pairs;
+    p.seq = ld.seq;
+    p.pos = ld.pos;
+    p.orig = ld.orig;
+    p.fam_base = fb;
+    p.ncols = ncols;
+    p.colmap_base = cm;
+    p.rowbase_base = rb;
+    plain_pairs += ncols - 1 - ld.pos;
+    pr.push_back(p);
+    wl.w64max_plain = std::max(wl.w64max_plain, (len[ld.seq] + 63u) / 64u);
+  };
+
+  for (const StepFamily& sf : fams) {
+    const uint32_t fb = sf.fam.fam_base, k = sf.fam.k;
+    if (k < 2) continue;
+    if (sf.whole && !plain_only) {
+      const uint32_t rb_base = (uint32_t)wl.rowbase.size();
+      wl.rowbase.resize(rb_base + k, 0);
+      for (const TileWork& t : sf.tiles)
+        for (uint32_t i = t.r0; i < t.r1; ++i) wl.rowbase[rb_base + i] = t.out_off + tri_rows(k, t.r0, i);
+      std::vector<uint32_t> perm(k);
+      std::iota(perm.begin(), perm.end(), 0u);
+      std::stable_sort(perm.begin(), perm.end(),
+                       [&](uint32_t a, uint32_t b) { return len[fb + a] > len[fb + b]; });
+      const uint32_t cm_base = (uint32_t)wl.colmap.size();
+      wl.colmap.insert(wl.colmap.end(), perm.begin(), perm.end());
+      colprefs.emplace_back(k + 1, 0);
+      std::vector<uint64_t>& cp = colprefs.back();
+      for (uint32_t q = 0; q < k; ++q) cp[q + 1] = cp[q] + len[fb + perm[q]];
+      for (uint32_t P = 0; P + 1 < k; P += kLanes) {
+        const uint32_t nrows = std::min<uint32_t>(kLanes, k - P);
+        const uint32_t W = std::max<uint32_t>(1, (len[fb + perm[P]] + 31) / 32);
+        GroupDesc g{};
+        g.lane_first = (uint32_t)wl.lanes.size();
+        g.nrows = nrows;
+        g.W = W;
+        g.fam_base = fb;
+        g.colmap_base = cm_base;
+        g.rowbase_base = rb_base;
+        const int cls = plain_only ? 3 : class_of(W, sigma);
+        for (uint32_t l = 0; l < nrows; ++l) {
+          const uint32_t a = perm[P + l];
+          LaneDesc ld{wl.rowbase[rb_base + a], fb + a, P + l, a, 0};
+          wl.cells[cls] += (uint64_t)len[fb + a] * (cp[k] - cp[P + l + 1]);
+          if (cls < 3) wl.lanes.push_back(ld);
+          else add_plain(ld, fb, k, cm_base, rb_base);
+        }
+        if (cls < 3) {
+          pend.push_back(PendingGroup{g, P + 1, k, cp.data(), 0});
+          span += k - (P + 1);
+        }
+      }
+    } else {
+      for (const TileWork& t : sf.tiles) {
+        std::vector<uint32_t> rows(t.r1 - t.r0);
+        std::iota(rows.begin(), rows.end(), t.r0);
+        if (!plain_only)
+          std::stable_sort(rows.begin(), rows.end(),
+                           [&](uint32_t a, uint32_t b) { return len[fb + a] > len[fb + b]; });
+        for (size_t P = 0; P < rows.size(); P += kLanes) {
+          const uint32_t nrows = (uint32_t)std::min<size_t>(kLanes, rows.size() - P);
+          uint32_t maxlen = 0, mini = 0xFFFFFFFFu;
+          for (uint32_t l = 0; l < nrows; ++l) {
+            maxlen = std::max(maxlen, len[fb + rows[P + l]]);
+            mini = std::min(mini, rows[P + l]);
+          }
+          if (mini + 1 >= k) continue;  // only the last row: no pairs
+          const uint32_t W = std::max<uint32_t>(1, (maxlen + 31) / 32);
+          GroupDesc g{};
+          g.lane_first = (uint32_t)wl.lanes.size();
+          g.nrows = nrows;
+          g.W = W;
+          g.fam_base = fb;
+          g.colmap_base = kNoMap;
+          g.rowbase_base = kNoMap;
+          const int cls = plain_only ? 3 : class_of(W, sigma);
+          for (uint32_t l = 0; l < nrows; ++l) {
+            const uint32_t i = rows[P + l];
+            LaneDesc ld{t.out_off + tri_rows(k, t.r0, i), fb + i, i, i, 0};
+            wl.cells[cls] += (uint64_t)len[fb + i] * (lenprefix[fb + k] - lenprefix[fb + i + 1]);
+            if (cls < 3) wl.lanes.push_back(ld);
+            else add_plain(ld, fb, k, kNoMap, kNoMap);
+          }
+          if (cls < 3) {
+            pend.push_back(PendingGroup{g, mini + 1, k, nullptr, lenprefix[fb]});
+            span += k - (mini + 1);
+          }
+        }
+      }
+    }
+  }
+
+  // column chunk: the configured size, smaller when the step is small so
+  // there are enough work items to fill the GPU
+  uint32_t C = lp.cols_per_item ? lp.cols_per_item : 256;
+  const uint64_t want_items = 4096;
+  if (span / C < want_items) C = (uint32_t)std::max<uint64_t>(16, std::min<uint64_t>(C, span / want_items));
+  for (const PendingGroup& pg : pend) {
+    const uint32_t gi = (uint32_t)wl.groups.size();
+    wl.groups.push_back(pg.g);
+    const int cls = class_of(pg.g.W, sigma);
+    wl.wmax[cls] = std::max(wl.wmax[cls], pg.g.W);
+    for (uint32_t c = pg.c0; c < pg.c1; c += C) {
+      const uint32_t c1 = std::min<uint32_t>(pg.c1, c + C);
+      uint64_t colsum;
+      if (pg.colpref) colsum = pg.colpref[c1] - pg.colpref[c];
+      else colsum = lenprefix[pg.g.fam_base + c1] - lenprefix[pg.g.fam_base + c];
+      ci[cls].push_back(CostItem{(uint64_t)pg.g.W * colsum + 64, ItemDesc{gi, c, c1, 0}});
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    std::stable_sort(ci[c].begin(), ci[c].end(), [](const CostItem& a, const CostItem& b) { return a.cost > b.cost; });
+    r.begin[c] = (uint32_t)wl.items.size();
+    for (const CostItem& x : ci[c]) wl.items.push_back(x.it);
+    r.end[c] = (uint32_t)wl.items.size();
+  }
+  r.begin[3] = (uint32_t)wl.prows.size();
+  wl.prows.insert(wl.prows.end(), pr.begin(), pr.end());
+  r.end[3] = (uint32_t)wl.prows.size();
+  r.plain_pairs = plain_pairs;
+  wl.max_plain_pairs = std::max(wl.max_plain_pairs, plain_pairs);
+  wl.ranges.push_back(r);
+}
+
+int gpu_info(int device, GpuInfo* gi) {
+  hipDeviceProp_t prop;
+  FAMSA_HIP(hipGetDeviceProperties(&prop, device));
+  gi->cus = prop.multiProcessorCount;
+  gi->arch = prop.gcnArchName;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    g_max_lds = std::min<size_t>(kMaxLds, (size_t)lds);
+  return 0;
+}
+
+int StepExec::prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint32_t sig) {
+  sigma = sig;
+  for (int c = 0; c < 3; ++c) {
+    wmax[c] = wl.wmax[c];
+    waves[c] = lp.waves[c];
+    blocks[c] = 0;
+    if (!wmax[c]) continue;
+    int bpc = 0;
+    int e = fast_prepare(c, sigma, wmax[c], waves[c], &bpc);
+    if (e)
+      return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup (sigma %u, W %u, %u waves) failed: %s", c, sigma,
+                       wmax[c], waves[c], hipGetErrorString((hipError_t)e));
+    while (bpc == 0 && waves[c] > 1) {  // too many waves for the registers: shrink the workgroup
+      waves[c] /= 2;
+      e = fast_prepare(c, sigma, wmax[c], waves[c], &bpc);
+      if (e) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup failed", c);
+    }
+    if (bpc == 0) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d cannot be resident", c);
+    blocks[c] = (uint32_t)(bpc * cus);
+  }
+  w64max_plain = wl.prows.empty() ? 0 : std::max<uint32_t>(1, wl.w64max_plain);
+  plain_blocks = wl.prows.empty() ? 0 : (uint32_t)(cus * 8);
+  return 0;
+}
+
+int StepExec::enqueue(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint64_t* plain_work,
+                      hipStream_t s, hipEvent_t* ev) const {
+  int e = launch_step_begin(ctl, s);
+  if (e) return set_error(FAMSA_LCS_EDEVICE, "step_begin launch failed: %s", hipGetErrorString((hipError_t)e));
+  for (int c = 0; c < 3; ++c) {
+    if (!wmax[c]) continue;
+    if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c], s));
+    e = launch_fast(c, b, w, ctl, out, sigma, wmax[c], blocks[c], waves[c], s);
+    if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_fast<%d> launch failed: %s", c, hipGetErrorString((hipError_t)e));
+    if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c + 1], s));
+  }
+  if (plain_blocks) {
+    if (ev) FAMSA_HIP(hipEventRecord(ev[6], s));
+    e = launch_plain(b, w, ctl, out, w64max_plain, plain_blocks, plain_work, s);
+    if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_plain launch failed: %s", hipGetErrorString((hipError_t)e));
+    if (ev) FAMSA_HIP(hipEventRecord(ev[7], s));
+  }
+  return 0;
+}
+
+}  // namespace famsa

@@ -1,0 +1,163 @@
+// Host runtime internals shared by the plan, the serving loop and the tuner.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/famsa_lcs.h"
+#include "lcs_common.h"
+
+namespace famsa {
+
+int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define FAMSA_HIP(call)                                                                                    \
+  do {                                                                                                     \
+    hipError_t e_ = (call);                                                                                \
+    if (e_ != hipSuccess) return ::famsa::set_error(FAMSA_LCS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// RAII device / pinned buffers.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { reset(); }
+  void reset();
+  int alloc(size_t n);  // 0 or FAMSA_LCS_ENOMEM / EDEVICE (error text set)
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinMem() = default;
+  PinMem(const PinMem&) = delete;
+  PinMem& operator=(const PinMem&) = delete;
+  ~PinMem() { reset(); }
+  void reset();
+  int alloc(size_t n);
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+int upload(DevMem& d, const std::vector<T>& h, hipStream_t s) {
+  const size_t n = h.size() * sizeof(T);
+  int rc = d.alloc(n ? n : sizeof(T));
+  if (rc) return rc;
+  if (n) FAMSA_HIP(hipMemcpyAsync(d.p, h.data(), n, hipMemcpyHostToDevice, s));
+  return 0;
+}
+
+// Normalised options.
+struct Opts {
+  uint32_t sigma = 20;
+  uint32_t tile_rows = 1024;
+  int device = 0;
+  hipStream_t user_stream = nullptr;
+  uint64_t hbm_budget = 0;
+  uint32_t flags = 0;
+  uint32_t cols_per_item = 0;
+  uint64_t step_values = 0;
+};
+int normalize_options(const famsa_lcs_options* in, Opts* out);
+
+// Host-side checks of one batch (no HIP calls).
+int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, const uint32_t* fam_off,
+                   uint32_t nfam, uint32_t sigma, std::vector<uint32_t>* fam_out, uint32_t* max_len);
+
+// A batch resident on the device with its masks.
+struct DeviceBatchOwner {
+  DevMem codes, dev_off, len, mask_off, masks, wprefix;
+  std::vector<uint32_t> h_len;       // per sequence
+  std::vector<uint64_t> h_lenprefix; // prefix sums of lengths (nseq + 1)
+  uint32_t nseq = 0, max_len = 0, sigma = 0;
+  uint64_t bytes = 0;
+  DeviceBatch view() const;
+  // Copies the batch (validated) to the device and builds the masks on `s`.
+  int create(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, uint32_t sigma, hipStream_t s);
+  static uint64_t footprint(const uint64_t* seq_off, uint32_t nseq, uint32_t sigma);
+};
+
+// A row tile to compute inside a launch step.
+struct TileWork {
+  uint32_t fam_base;     // global index of the family's first sequence
+  uint32_t k;            // family size
+  uint32_t r0, r1;       // rows
+  uint64_t out_off;      // step-buffer offset of the tile
+};
+
+struct LaunchParams {
+  uint32_t waves[3] = {4, 8, 16};  // wavefronts per workgroup per class
+  uint32_t cols_per_item = 256;
+};
+
+// Host copies of the descriptor arrays for one or more steps.
+struct WorkLists {
+  std::vector<GroupDesc> groups;
+  std::vector<LaneDesc> lanes;
+  std::vector<ItemDesc> items;
+  std::vector<PlainRow> prows;
+  std::vector<uint32_t> colmap;
+  std::vector<uint64_t> rowbase;
+  std::vector<StepRange> ranges;
+  uint32_t wmax[3] = {0, 0, 0};   // largest W per fast class
+  uint32_t w64max_plain = 0;       // largest ceil(len/64) in plain rows
+  uint64_t cells[4] = {0, 0, 0, 0};
+  uint64_t max_plain_pairs = 0;
+};
+
+struct FamilyRef {
+  uint32_t fam_base, k;
+};
+
+// Appends one step.  `tiles` lists the step's tiles; a family all of whose
+// tiles are in the step (whole == true) uses family mode.  `plain_only`
+// sends every row to the plain kernel (baseline).
+struct StepFamily {
+  FamilyRef fam;
+  bool whole;                       // all tiles of the family are in this step
+  std::vector<TileWork> tiles;      // this family's tiles in the step
+};
+void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::vector<uint32_t>& len,
+                const std::vector<uint64_t>& lenprefix, uint32_t sigma, const LaunchParams& lp, bool plain_only);
+
+// Element count of rows [r0, r1) of a k-family upper triangle.
+inline uint64_t tri_rows(uint64_t k, uint64_t r0, uint64_t r1) {
+  if (r1 > k) r1 = k;
+  if (r0 >= r1) return 0;
+  // sum_{i=r0}^{r1-1} (k-1-i)
+  const uint64_t n = r1 - r0;
+  return n * (k - 1) - (r0 + r1 - 1) * n / 2;
+}
+
+struct GpuInfo {
+  int cus = 256;
+  std::string arch;
+};
+int gpu_info(int device, GpuInfo* gi);
+
+// Class of a group with W dwords per lane (3 = plain).
+int class_of(uint32_t W, uint32_t sigma);
+
+// Executes the launches of one step for a set of descriptor arrays.
+struct StepExec {
+  uint32_t sigma = 20;
+  uint32_t wmax[3] = {0, 0, 0};
+  uint32_t waves[3] = {4, 8, 16};
+  uint32_t blocks[3] = {0, 0, 0};
+  uint32_t plain_blocks = 0;
+  uint32_t w64max_plain = 0;
+  int prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint32_t sigma);
+  // Enqueue one step: step_begin + class kernels (those with work in the
+  // plan) + plain.  With `ev` != NULL records per-kernel events (ev[2*c], ev[2*c+1]).
+  int enqueue(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint64_t* plain_work,
+              hipStream_t s, hipEvent_t* ev) const;
+};
+
+}  // namespace famsa

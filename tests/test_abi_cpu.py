@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/famsa_lcs.h declares, and rejects invalid input with EINVAL before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1603_06958_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "famsa_lcs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(famsa_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 19, names
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def plan_rc(codes, off, fam=None, nfam=0, **opt):
+    L = B.lib()
+    o = B.make_options(**opt)
+    h = ctypes.c_void_p(123)
+    codes = np.ascontiguousarray(codes, np.uint8)
+    off = np.ascontiguousarray(off, np.uint64)
+    cp = codes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if codes.size else None
+    fp = None
+    if fam is not None:
+        fam = np.ascontiguousarray(fam, np.uint32)
+        fp = fam.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    rc = L.famsa_lcs_plan(cp, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), off.size - 1, fp, nfam,
+                          ctypes.byref(o), ctypes.byref(h))
+    if rc == 0:
+        L.famsa_lcs_release(h)
+    else:
+        assert not h.value  # out is cleared on failure
+    return rc, B.last_error()
+
+
+def test_einval_code_out_of_alphabet():
+    rc, msg = plan_rc([1, 2, 20], [0, 3])
+    assert rc == B.EINVAL and "alphabet" in msg
+
+
+def test_einval_alphabet_size():
+    assert plan_rc([0], [0, 1], alphabet_size=0)[0] == B.EINVAL
+    assert plan_rc([0], [0, 1], alphabet_size=33)[0] == B.EINVAL
+    # codes up to 31 are fine with alphabet 32 (fails later only for lack of a GPU)
+    assert plan_rc([31, 0], [0, 2], alphabet_size=32)[0] != B.EINVAL
+
+
+def test_einval_offsets():
+    assert plan_rc([0, 1, 2], [0, 2, 1])[0] == B.EINVAL
+    long = np.zeros(B.MAX_LEN + 1, np.uint8)
+    rc, msg = plan_rc(long, [0, long.size])
+    assert rc == B.EINVAL and "length" in msg
+
+
+def test_einval_families():
+    c = np.zeros(4, np.uint8)
+    off = [0, 1, 2, 3, 4]
+    assert plan_rc(c, off, fam=[1, 4], nfam=1)[0] == B.EINVAL      # fam_off[0] != 0
+    assert plan_rc(c, off, fam=[0, 3], nfam=1)[0] == B.EINVAL      # does not end at nseq
+    assert plan_rc(c, off, fam=[0, 3, 2, 4], nfam=3)[0] == B.EINVAL  # decreasing
+
+
+def test_einval_options():
+    assert plan_rc([0], [0, 1], tile_rows=0)[0] == B.EINVAL
+    assert plan_rc([0], [0, 1], flags=0x100)[0] == B.EINVAL
+    L = B.lib()
+    o = B.make_options()
+    o.struct_size = 4
+    h = ctypes.c_void_p()
+    off = np.array([0, 1], np.uint64)
+    c = np.zeros(1, np.uint8)
+    rc = L.famsa_lcs_plan(c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                          off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 1, None, 0, ctypes.byref(o),
+                          ctypes.byref(h))
+    assert rc == B.EINVAL and "struct_size" in B.last_error()
+
+
+def test_null_arguments():
+    L = B.lib()
+    off = np.array([0, 1], np.uint64)
+    assert L.famsa_lcs_plan(None, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 1, None, 0, None,
+                            None) == B.EINVAL
+    h = ctypes.c_void_p()
+    # residues present but codes NULL
+    assert L.famsa_lcs_plan(None, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 1, None, 0, None,
+                            ctypes.byref(h)) == B.EINVAL
+    L.famsa_lcs_release(None)  # no-op
+    assert L.famsa_lcs_tiles(None, 0, B.TILE_FN(lambda u, t: 0), None) == B.EINVAL
+    assert L.famsa_lcs_plan_get_info(None, None) == B.EINVAL
+    L.famsa_slink_destroy(None)
+    L.famsa_lcs_server_destroy(None)
+
+
+def test_no_gpu_is_edevice():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    rc, msg = plan_rc([0, 1, 2], [0, 3])
+    assert rc == B.EDEVICE, msg
