@@ -1,0 +1,211 @@
+"""Benchmark of the all-pairs LCS similarity stage on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c1]
+                    [--no-c3] [--no-serve] [--no-cpu]
+
+One step = one full pass of the stage over the workload: every row tile of
+the family computed on the GPU (masks resident in HBM; the plan is built
+before the timed region) and copied to pinned host memory, where the tile
+callback receives it.  `value` is GCUPS = sum over pairs of |A||B| divided
+by the wall time of a step.  Also reported, in the same JSON line:
+
+* roofline: the dominant LCS kernel's integer-ALU throughput (3 VALU ops
+  per 32 cells: AND, ADD-with-carry, the three-input OR/AND-NOT) against
+  gfx950's 256 CUs x 64 lanes x 2.4 GHz, from HIP events around each launch
+  on its own stream during the timed steps;
+* cpu_baseline: the CPU oracle (plain DP) on a bounded sample of the same
+  workload's pairs, on the host's cores;
+* c3: batched (persistent, graph-replayed) vs plain per-family launches;
+* serve: continuous-batching jobs, pairs/s and p50/p99 latency.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "GCUPS for all-pairs bit-parallel LCS (k=100k), batched vs plain; serve p99 ms"
+PEAK_INT_OPS = 256 * 64 * 2.4e9       # int32 VALU lane-ops/s on MI355X (256 CUs, 64 lanes, 2.4 GHz)
+OPS_PER_CELL = 3.0 / 32.0             # AND + ADDC + BITOP3 per 32-cell dword-step
+
+
+def _oracle_worker(args):
+    codes, off, ia, ib = args
+    import oracle
+    t0 = time.perf_counter()
+    oracle.lcs_pairs(codes, off, ia, ib)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(b, seconds_target=12.0, seed=7):
+    """The oracle on a seeded sample of the workload's pairs, one process per core."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    L = b.lengths().astype(np.int64)
+    k = b.nseq
+    # calibrate on a small sample (single core)
+    ia = rng.integers(0, k, 200)
+    ib = rng.integers(0, k, 200)
+    t0 = time.perf_counter()
+    oracle.lcs_pairs(b.codes, b.seq_off, ia, ib)
+    dt = time.perf_counter() - t0
+    rate1 = float((L[ia] * L[ib]).sum()) / max(dt, 1e-9)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    per_worker_cells = rate1 * seconds_target
+    mean_cells = float((L.mean()) ** 2)
+    npw = max(50, int(per_worker_cells / mean_cells))
+    jobs = []
+    cells = 0
+    for _ in range(cores):
+        a = rng.integers(0, k, npw)
+        c = rng.integers(0, k, npw)
+        cells += int((L[a] * L[c]).sum())
+        jobs.append((b.codes, b.seq_off, a, c))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    return {"value": cells / wall / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{cores * npw} random pairs of the workload (seed {seed}), {cells:.3e} cells, "
+                      f"{cores} single-threaded processes, {wall:.1f} s wall"}
+
+
+def run_main(b, steps, warmup, tile_rows=1024):
+    from paper_1603_06958_amd import binding as B
+    import torch
+    p = B.Plan.from_batch(b, tile_rows=tile_rows, flags=B.NO_GRAPH)
+    info = p.info()
+    sink = [0]
+
+    def fn(t):
+        sink[0] += int(t.count)
+        return 0
+
+    for _ in range(warmup):
+        p.run(fn)
+    torch.cuda.synchronize()
+    times, kstats = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.run(fn)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        kstats.append(p.stats())
+    p.close()
+    return info, times, kstats, sink[0]
+
+
+def run_c3(steps=1):
+    from paper_1603_06958_amd import binding as B, inputs
+    b = inputs.c3()
+    out = {"workload": "c3: 64 tree-evolved families, k log-uniform [50,5000], root length log-uniform [30,2000]",
+           "pairs": b.pairs(), "cells": b.cells()}
+    res = {}
+    for name, flags in [("batched", 0), ("plain", B.PLAIN)]:
+        p = B.Plan.from_batch(b, flags=flags)
+        chk = [0]
+
+        def fn(t):
+            chk[0] += int(t.count)
+            return 0
+
+        p.run(fn)  # warm-up
+        best = None
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            p.run(fn)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        res[name] = best
+        out[f"{name}_s"] = round(best, 4)
+        out[f"{name}_gcups"] = round(b.cells() / best / 1e9, 1)
+        p.close()
+    out["batched_over_plain"] = round(res["plain"] / res["batched"], 2)
+    return out
+
+
+def run_serve():
+    from paper_1603_06958_amd import serve
+    return serve.run_c5_bench()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c4"])
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the stage on a single MI355X "
+              "(the multi-GPU sharding is a design, not a run); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    from paper_1603_06958_amd import inputs
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    b = inputs.WORKLOADS[a.workload]()
+    print(f"[bench] generated {a.workload} in {time.time() - t0:.1f}s: {inputs.stats(b)}", file=sys.stderr,
+          flush=True)
+    info, times, kst, count = run_main(b, a.steps, a.warmup)
+    cells = info.cells
+    ms = 1e3 * float(np.mean(times))
+    value = cells / (ms / 1e3) / 1e9
+    # dominant kernel: the fast class with the most cells
+    cls = int(np.argmax([kst[-1].cells[c] for c in range(3)]))
+    kms = float(np.mean([s.kernel_ms[cls] / max(1, s.launches[cls]) for s in kst]))
+    per_launch_cells = kst[-1].cells[cls] / max(1, kst[-1].launches[cls])
+    achieved = per_launch_cells * OPS_PER_CELL / (kms / 1e3)
+    print(f"[bench] steps {[round(t, 3) for t in times]} s; kernel classes ms "
+          f"{[round(x, 1) for x in kst[-1].kernel_ms]} launches {list(kst[-1].launches)} "
+          f"step_ms {kst[-1].step_ms:.1f}", file=sys.stderr, flush=True)
+    res = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GCUPS", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": {"c4": "c4: one tree-evolved family, k=100000, root 250, log-normal lengths "
+                                      "(median 250, sigma 0.3, clip [40,1500]), seed 3",
+                                "c2": "c2: one tree-evolved family, k=10000, root 300, seed 1",
+                                "c1": "c1: k=100 i.i.d., lengths U[50,300], seed 0"}[a.workload],
+                   "k": b.nseq, "pairs": info.pairs, "cells": cells, "tile_rows": 1024,
+                   "delivery": "host pinned memory, callback per tile"},
+        "pairs_per_s": round(info.pairs / (ms / 1e3), 1),
+        "device_gcups": round(cells / (kst[-1].step_ms / 1e3) / 1e9, 1),
+        "peak_hbm_bytes": int(info.device_bytes),
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_INT_OPS / 1e12, 3),
+                     "unit": "Tops/s (int32 VALU)", "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": None,
+                     "kernel": f"lcs_fast_kernel<{cls}>", "avg_launch_ms": round(kms, 3),
+                     "cells_per_launch": int(per_launch_cells)},
+    }
+    if not a.no_c3:
+        res["c3"] = run_c3()
+        print(f"[bench] c3 {res['c3']}", file=sys.stderr, flush=True)
+    if not a.no_serve:
+        try:
+            res["serve"] = run_serve()
+        except Exception as e:  # report, do not hide
+            res["serve"] = {"error": str(e)}
+        print(f"[bench] serve {res['serve']}", file=sys.stderr, flush=True)
+    if not a.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(b)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -40,4 +40,26 @@ int tune_lookup(const GpuInfo& gi, uint32_t sigma, LaunchParams* lp) {
   return 0;
 }
 
+int tune_store(const GpuInfo& gi, uint32_t sigma, const LaunchParams& lp, const char* path) {
+  if (!path || !*path) path = getenv("FAMSA_LCS_TUNE_CACHE");
+  if (!path || !*path) return 0;
+  const std::string key = cache_key(gi, sigma);
+  std::string keep;
+  if (FILE* f = fopen(path, "r")) {
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+      char k[256];
+      if (sscanf(line, "%255s", k) == 1 && key == k) continue;
+      keep += line;
+    }
+    fclose(f);
+  }
+  FILE* f = fopen(path, "w");
+  if (!f) return set_error(FAMSA_LCS_EINVAL, "cannot write tuning cache %s", path);
+  fputs(keep.c_str(), f);
+  fprintf(f, "%s %u %u %u %u\n", key.c_str(), lp.waves[0], lp.waves[1], lp.waves[2], lp.cols_per_item);
+  fclose(f);
+  return 0;
+}
+
 }  // namespace famsa

@@ -18,6 +18,7 @@
 namespace famsa {
 const char* last_error_text();
 int tune_lookup(const GpuInfo& gi, uint32_t sigma, LaunchParams* lp);
+int tune_store(const GpuInfo& gi, uint32_t sigma, const LaunchParams& lp, const char* path);
 }  // namespace famsa
 
 using namespace famsa;
@@ -69,6 +70,8 @@ struct famsa_lcs_plan_s {
   int setup_device();
   int capture_graphs();
   int enqueue_step(uint64_t s, int slot, bool timed);
+  int upload_work();
+  int autotune(const char* path);
   int run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user);
 };
 
@@ -239,6 +242,110 @@ int famsa_lcs_plan_s::enqueue_step(uint64_t s, int slot, bool timed) {
   return 0;
 }
 
+int famsa_lcs_plan_s::upload_work() {
+  hipStream_t s = cs[0];
+  int rc;
+  if ((rc = upload(d_groups, wl.groups, s)) || (rc = upload(d_lanes, wl.lanes, s)) || (rc = upload(d_items, wl.items, s)) ||
+      (rc = upload(d_prows, wl.prows, s)) || (rc = upload(d_colmap, wl.colmap, s)) ||
+      (rc = upload(d_rowbase, wl.rowbase, s)) || (rc = upload(d_ranges, wl.ranges, s)))
+    return rc;
+  FAMSA_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+// Time every candidate (columns per item x waves per workgroup of each
+// length class) on the plan's first step, one class kernel at a time with
+// events around it, keep the fastest, and rebuild the plan with it.
+int famsa_lcs_plan_s::autotune(const char* path) {
+  if (plain() || steps.empty()) return 0;
+  static const uint32_t kCols[] = {64, 128, 256, 512};
+  static const uint32_t kWaves[3][3] = {{2, 4, 8}, {4, 8, 16}, {8, 16, 16}};
+  hipStream_t st = cs[0];
+  hipEvent_t e0 = ev_k[0][0], e1 = ev_k[0][1];
+  double best_total = 1e300;
+  LaunchParams best = lp;
+  std::vector<StepFamily> fams;  // step 0
+  for (uint64_t t = steps[0].tile_begin; t < steps[0].tile_end; ++t) {
+    const Tile& tl = tiles[t];
+    const uint32_t fb = fam_off[tl.fam], k = fam_off[tl.fam + 1] - fb;
+    if (fams.empty() || fams.back().fam.fam_base != fb) {
+      StepFamily sf;
+      sf.fam = FamilyRef{fb, k};
+      sf.whole = tri_rows(k, 0, k) <= step_cap;
+      fams.push_back(sf);
+    }
+    fams.back().tiles.push_back(TileWork{fb, k, tl.r0, tl.r1, tl.out_off});
+  }
+  DevMem tg, tl_, ti, tp, tc, tr, tra;
+  for (uint32_t cols : kCols) {
+    LaunchParams cand = lp;
+    cand.cols_per_item = cols;
+    WorkLists w1;
+    build_step(w1, fams, batch.h_len, batch.h_lenprefix, opt.sigma, cand, false);
+    int rc;
+    if ((rc = upload(tg, w1.groups, st)) || (rc = upload(tl_, w1.lanes, st)) || (rc = upload(ti, w1.items, st)) ||
+        (rc = upload(tp, w1.prows, st)) || (rc = upload(tc, w1.colmap, st)) || (rc = upload(tr, w1.rowbase, st)) ||
+        (rc = upload(tra, w1.ranges, st)))
+      return rc;
+    const DeviceWork w{tg.as<GroupDesc>(), tl_.as<LaneDesc>(), ti.as<ItemDesc>(), tp.as<PlainRow>(), tc.as<uint32_t>(),
+                       tr.as<uint64_t>(), tra.as<StepRange>()};
+    double total = 0;
+    for (int c = 0; c < 3; ++c) {
+      if (!w1.wmax[c]) continue;
+      double bc = 1e300;
+      uint32_t bw = cand.waves[c];
+      for (uint32_t wv : kWaves[c]) {
+        int bpc = 0;
+        if (fast_prepare(c, opt.sigma, w1.wmax[c], wv, &bpc) || bpc == 0) continue;
+        StepCtl hc{};
+        hc.next_step = 0;
+        hc.stride = 1;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          FAMSA_HIP(hipMemcpyAsync(d_ctl.p, &hc, sizeof hc, hipMemcpyHostToDevice, st));
+          if (launch_step_begin(ctl(0), st)) return set_error(FAMSA_LCS_EDEVICE, "step_begin failed");
+          FAMSA_HIP(hipEventRecord(e0, st));
+          if (launch_fast(c, batch.view(), w, ctl(0), d_out[0].as<int32_t>(), opt.sigma, w1.wmax[c],
+                          (uint32_t)(bpc * gi.cus), wv, st))
+            return set_error(FAMSA_LCS_EDEVICE, "tuning launch failed");
+          FAMSA_HIP(hipEventRecord(e1, st));
+          FAMSA_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          FAMSA_HIP(hipEventElapsedTime(&ms, e0, e1));
+          best_ms = std::min(best_ms, ms);
+        }
+        if (best_ms < bc) {
+          bc = best_ms;
+          bw = wv;
+        }
+      }
+      cand.waves[c] = bw;
+      total += bc;
+    }
+    if (total < best_total) {
+      best_total = total;
+      best = cand;
+    }
+  }
+  lp = best;
+  int rc;
+  if ((rc = tune_store(gi, opt.sigma, lp, path))) return rc;
+  // rebuild the work lists, launch shapes and graphs with the winner
+  for (int i = 0; i < 2; ++i)
+    if (graph[i]) {
+      (void)hipGraphExecDestroy(graph[i]);
+      graph[i] = nullptr;
+    }
+  wl = WorkLists();
+  if ((rc = build_work())) return rc;
+  if ((rc = upload_work())) return rc;
+  if ((rc = exec.prepare(gi.cus, lp, wl, opt.sigma))) return rc;
+  if (exec.w64max_plain > plain_register_w64_limit())
+    exec.plain_blocks = std::min<uint32_t>(exec.plain_blocks, (uint32_t)gi.cus * 8u);
+  if (use_graph() && (rc = capture_graphs())) return rc;
+  return 0;
+}
+
 static double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -253,11 +360,14 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
   const int nslots = plain() ? 1 : 2;
   FAMSA_HIP(hipSetDevice(opt.device));
   // the first step each control block computes, and its stride
+  // step s runs on slot s % nslots: seed each slot's control block with the
+  // first step it will see
   StepCtl hc[2] = {};
-  hc[0].next_step = (uint32_t)s0;
-  hc[0].stride = (uint32_t)nslots;
-  hc[1].next_step = (uint32_t)s0 + 1;
-  hc[1].stride = (uint32_t)nslots;
+  for (uint64_t s = s0; s < s0 + 2; ++s) {
+    hc[s % nslots].next_step = (uint32_t)s;
+    hc[s % nslots].stride = (uint32_t)nslots;
+    if (nslots == 1) break;
+  }
   FAMSA_HIP(hipMemcpy(d_ctl.p, hc, sizeof hc, hipMemcpyHostToDevice));
   if (opt.user_stream) {
     FAMSA_HIP(hipEventRecord(ev_user, opt.user_stream));
@@ -404,11 +514,7 @@ int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
   if ((rc = p->setup_device())) return fail(rc);
   if ((rc = p->batch.create(codes, seq_off, nseq, o.sigma, p->cs[0]))) return fail(rc);
   hipStream_t s = p->cs[0];
-  if ((rc = upload(p->d_groups, p->wl.groups, s)) || (rc = upload(p->d_lanes, p->wl.lanes, s)) ||
-      (rc = upload(p->d_items, p->wl.items, s)) || (rc = upload(p->d_prows, p->wl.prows, s)) ||
-      (rc = upload(p->d_colmap, p->wl.colmap, s)) || (rc = upload(p->d_rowbase, p->wl.rowbase, s)) ||
-      (rc = upload(p->d_ranges, p->wl.ranges, s)))
-    return fail(rc);
+  if ((rc = p->upload_work())) return fail(rc);
   if ((rc = p->d_ctl.alloc(2 * sizeof(StepCtl)))) return fail(rc);
   uint64_t step_max = 0;
   for (const auto& st : p->steps) step_max = std::max(step_max, st.values);
@@ -472,6 +578,16 @@ int famsa_lcs_tiles(famsa_lcs_plan_t* p, uint64_t first_tile, famsa_lcs_tile_fn 
 }
 
 void famsa_lcs_release(famsa_lcs_plan_t* p) { delete p; }
+
+int famsa_lcs_autotune(famsa_lcs_plan_t* p, const char* cache_path) {
+  clear_error();
+  if (!p) return set_error(FAMSA_LCS_EINVAL, "plan is NULL");
+  int expect = 0;
+  if (!p->busy.compare_exchange_strong(expect, 1)) return set_error(FAMSA_LCS_EBUSY, "plan is already running");
+  int rc = p->autotune(cache_path);
+  p->busy.store(0);
+  return rc;
+}
 
 int famsa_lcs_plan_get_info(const famsa_lcs_plan_t* p, famsa_lcs_plan_info* info) {
   clear_error();

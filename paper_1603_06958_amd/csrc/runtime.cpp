@@ -185,6 +185,8 @@ int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uin
   if ((rc = upload(mask_off, hmo, s))) return rc;
   if ((rc = upload(wprefix, hwp, s))) return rc;
   if ((rc = masks.alloc(mw * 4 + 16))) return rc;
+  h_dev_off = hoff;
+  h_mask_off = hmo;
   const DeviceBatch v = view();
   int e = launch_build_masks(v, wprefix.as<uint64_t>(), n, words, sigma, masks.as<uint32_t>(), s);
   if (e) return set_error(FAMSA_LCS_EDEVICE, "build_masks launch failed: %s", hipGetErrorString((hipError_t)e));

@@ -76,6 +76,8 @@ struct DeviceBatchOwner {
   DevMem codes, dev_off, len, mask_off, masks, wprefix;
   std::vector<uint32_t> h_len;       // per sequence
   std::vector<uint64_t> h_lenprefix; // prefix sums of lengths (nseq + 1)
+  std::vector<uint64_t> h_dev_off;   // device byte offset of each sequence in `codes`
+  std::vector<uint64_t> h_mask_off;  // dword offset of each sequence's masks in `masks`
   uint32_t nseq = 0, max_len = 0, sigma = 0;
   uint64_t bytes = 0;
   DeviceBatch view() const;

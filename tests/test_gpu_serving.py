@@ -1,0 +1,72 @@
+"""Serving: every job's tiles are bit-exact against the oracle and identical
+to the same job run alone through a plan; a budget that fits one job at a
+time queues jobs instead of failing; a job that can never fit is refused."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_06958_amd import binding as B
+from paper_1603_06958_amd import inputs, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def small_jobs(n=9, seed=21):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    t = 0.0
+    for j in range(n):
+        k = int(rng.integers(2, 260))
+        b = inputs.random_family(k, 0, int(rng.integers(20, 1300)), seed + j)
+        jobs.append(inputs.ServeJob(t, b))
+        t += float(rng.exponential(0.002))
+    return jobs
+
+
+def collect(jobs, **opt):
+    got = {}
+
+    def on_tile(jid, t):
+        got[(jid, int(t.row_begin), int(t.row_end))] = B.tile_array(t).copy()
+
+    r = serve.run_jobs(jobs, on_tile=on_tile, **opt)
+    return got, r
+
+
+@pytest.mark.parametrize("R,step_values", [(64, 0), (16, 5000)])
+def test_serving_matches_oracle_and_alone(R, step_values):
+    jobs = small_jobs()
+    got, r = collect(jobs, tile_rows=R, step_values=step_values)
+    ids = r["job_ids"]
+    for jid, i in ids.items():
+        b = jobs[i].batch
+        k = b.nseq
+        with B.Plan.from_batch(b, tile_rows=R) as p:
+            alone = p.collect()
+        for r0 in range(0, k, R):
+            r1 = min(k, r0 + R)
+            mix = got[(jid, r0, r1)]
+            assert np.array_equal(mix, alone[(0, r0, r1)]), (jid, r0)
+            assert np.array_equal(mix, oracle.tile_expected(b.codes, b.seq_off, 0, k, r0, r1)), (jid, r0)
+
+
+def test_small_budget_queues():
+    jobs = small_jobs(5, seed=3)
+    # room for the step buffers and about one job
+    got, r = collect(jobs, tile_rows=64, step_values=20000, hbm_budget=2 * 20000 * 4 + (64 << 20) + 1_200_000)
+    assert r["jobs"] == 5
+    for jid, i in r["job_ids"].items():
+        b = jobs[i].batch
+        k = b.nseq
+        for r0 in range(0, k, 64):
+            exp = oracle.tile_expected(b.codes, b.seq_off, 0, k, r0, min(k, r0 + 64))
+            assert np.array_equal(got[(jid, r0, min(k, r0 + 64))], exp)
+
+
+def test_job_too_large_is_refused():
+    srv = serve.Server(step_values=4096, hbm_budget=2 * 4096 * 4 + (64 << 20) + 1000)
+    b = inputs.random_family(3000, 500, 900, 1)
+    with pytest.raises(B.FamsaError) as e:
+        srv.submit(b.codes, b.seq_off)
+    assert e.value.code == B.ENOMEM
+    srv.close()
