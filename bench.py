@@ -33,7 +33,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "GCUPS for all-pairs bit-parallel LCS (k=100k), batched vs plain; serve p99 ms"
-PEAK_INT_OPS = 256 * 64 * 2.4e9       # int32 VALU lane-ops/s on MI355X (256 CUs, 64 lanes, 2.4 GHz)
+# int32 VALU lane-ops/s of MI355X: 256 CUs x 128 lanes/clk x 2.4 GHz, the
+# fp32-vector lane rate (157.3 TFLOP/s / 2 flops per FMA); the measured VALU
+# instruction rate of the LCS kernels exceeds 64 lanes/clk/CU, so 64 is not
+# the ceiling.
+PEAK_INT_OPS = 256 * 128 * 2.4e9
 OPS_PER_CELL = 3.0 / 32.0             # AND + ADDC + BITOP3 per 32-cell dword-step
 
 
@@ -82,10 +86,15 @@ def cpu_baseline(b, seconds_target=12.0, seed=7):
                       f"{cores} single-threaded processes, {wall:.1f} s wall"}
 
 
-def run_main(b, steps, warmup, tile_rows=1024):
+def run_main(b, steps, warmup, tile_rows=1024, tune=True):
     from paper_1603_06958_amd import binding as B
     import torch
     p = B.Plan.from_batch(b, tile_rows=tile_rows, flags=B.NO_GRAPH)
+    if tune:
+        t0 = time.perf_counter()
+        p.autotune(os.environ.get("FAMSA_LCS_TUNE_CACHE") or None)
+        print(f"[bench] autotune {time.perf_counter() - t0:.2f}s -> cols {p.info().cols_per_item} "
+              f"waves {list(p.info().waves_per_group)[:3]}", file=sys.stderr, flush=True)
     info = p.info()
     sink = [0]
 
@@ -191,7 +200,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_INT_OPS / 1e12, 3),
                      "unit": "Tops/s (int32 VALU)", "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": None,
                      "kernel": f"lcs_fast_kernel<{cls}>", "avg_launch_ms": round(kms, 3),
-                     "cells_per_launch": int(per_launch_cells)},
+                     "cells_per_launch": int(per_launch_cells),
+                     "ops_per_cell": "3/32 (AND, ADDC, BITOP3 per 32-cell dword)"},
+        "launch": {"cols_per_item": int(info.cols_per_item), "waves_per_group": list(info.waves_per_group)[:3]},
     }
     if not a.no_c3:
         res["c3"] = run_c3()

@@ -50,8 +50,8 @@ class PlanInfo(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("kernel_ms", ctypes.c_double * 4), ("launches", ctypes.c_uint64 * 4),
-                ("cells", ctypes.c_uint64 * 4), ("step_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
+    _fields_ = [("kernel_ms", ctypes.c_double * 5), ("launches", ctypes.c_uint64 * 5),
+                ("cells", ctypes.c_uint64 * 5), ("step_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
                 ("wall_ms", ctypes.c_double), ("tiles", ctypes.c_uint64)]
 
 

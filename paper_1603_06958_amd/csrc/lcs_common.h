@@ -31,8 +31,8 @@
 namespace famsa {
 
 constexpr int kLanes = 64;        // wavefront size on gfx950
-constexpr int kNumClasses = 4;    // fast kernels by row length class + plain/fallback
-constexpr int kClassWMax[3] = {8, 16, 32};  // dwords per lane covered by classes 0..2
+constexpr int kNumClasses = 5;    // 0..2 fast kernels by row length, 3 segmented long-row kernel, 4 plain kernel
+constexpr int kClassQMax[3] = {2, 4, 7};   // 128-bit mask quads per lane covered by classes 0..2 (W <= 8, 16, 28)
 constexpr int kSeqAlign = 32;     // device code padding / alignment (bytes)
 constexpr size_t kMaxLds = 163840;  // LDS bytes per workgroup on gfx950 (capped by the device's own limit)
 extern size_t g_max_lds;          // min(kMaxLds, device limit), set when a plan or server opens a device
@@ -89,20 +89,31 @@ struct PlainRow {           // 48 bytes
 struct StepCtl {
   uint32_t step;            // step the current replay computes
   uint32_t next_step;       // step the next replay will compute
-  uint32_t cursor[4];       // work-queue cursors per class
+  uint32_t cursor[4];       // work-queue cursors of classes 0..3
   uint32_t stride;          // steps between consecutive replays on this block
   uint32_t pad;
 };
 
-struct StepRange {          // per step, per class 0..2: items; class 3: plain rows
-  uint32_t begin[4];
-  uint32_t end[4];
-  uint64_t plain_pairs;     // pairs in the class-3 row range
+struct StepRange {          // per step: classes 0..3 index items, class 4 indexes plain rows
+  uint32_t begin[5];
+  uint32_t end[5];
+  uint64_t plain_pairs;     // pairs in the class-4 row range
 };
+
+// Segmented long-row kernel: rows longer than the fast classes cover are cut
+// into segments of kLongSegQ[sigcap == 32] quads; the carry out of a
+// segment's top dword at each column step is passed to the next segment as
+// one bit per step through a scratch buffer of kLongCarryWords(n) dwords per
+// lane for a column of n residues.
+constexpr int kLongSegQ[2] = {7, 4};  // sigma <= 20, sigma <= 32
+inline uint32_t long_seg_q(uint32_t sigma) { return sigma <= 20 ? 7u : 4u; }
 
 struct DeviceBatch {
   const uint8_t* codes;
   const uint64_t* dev_off;
+  const uint8_t* sym;       // column streams: residue c stored as uint16 c * 1024 (its LDS plane offset)
+  const uint64_t* sym_off;  // byte offset of each sequence's stream; 16-byte aligned, padded with one
+                            // spare 16-byte chunk so the kernels may read one chunk ahead
   const uint32_t* len;
   const uint64_t* mask_off;
   const uint32_t* masks;
@@ -125,14 +136,20 @@ int launch_step_begin(StepCtl* ctl, void* stream);
 // Fast kernel for length class cls (0..2): persistent, `blocks` workgroups of
 // `waves` wavefronts each.
 int launch_fast(int cls, const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint32_t sigma,
-                uint32_t wmax, uint32_t blocks, uint32_t waves, void* stream);
-size_t fast_lds_bytes(uint32_t sigma, uint32_t wmax);
-int fast_prepare(int cls, uint32_t sigma, uint32_t wmax, uint32_t waves, int* blocks_per_cu);
+                uint32_t qmax, uint32_t blocks, uint32_t waves, void* stream);
+// LDS mask table of a fast kernel: qmax quads x sigcap symbols x 64 lanes x 16 bytes.
+inline uint32_t sig_cap(uint32_t sigma) { return sigma <= 20 ? 20u : 32u; }
+inline size_t fast_lds_bytes(uint32_t sigma, uint32_t qmax) { return (size_t)qmax * sig_cap(sigma) * 1024u; }
+int fast_prepare(int cls, uint32_t sigma, uint32_t qmax, uint32_t waves, int* blocks_per_cu);
 // Plain kernel: one pair per lane over the class-3 row range of the current
 // step; w64_max bounds ceil(len/64) of the rows; d_work is scratch for rows
 // longer than the register variants cover (may be NULL otherwise).
 int launch_plain(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint32_t w64_max,
                  uint32_t blocks, uint64_t* d_work, void* stream);
 uint32_t plain_register_w64_limit();
+// Long-row kernel: `carry` holds blocks*waves*carry_words*64 dwords.
+int launch_long(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint32_t sigma,
+                uint32_t* carry, uint32_t carry_words, uint32_t blocks, uint32_t waves, void* stream);
+int long_prepare(uint32_t sigma, uint32_t waves, int* blocks_per_cu);
 
 }  // namespace famsa

@@ -15,10 +15,11 @@
 // Three kernels:
 //  * build_masks   -- PM[c][w] for every sequence (one thread per dword).
 //  * lcs_fast<cls> -- one wavefront handles 64 rows (one per lane) against a
-//    single column sequence, so the column symbol is wave-uniform: it is
-//    fetched with scalar loads, and each lane reads its row's mask dwords
-//    for that symbol from LDS with 128-bit reads (lane-interleaved layout,
-//    conflict free).  Per 32 cells a lane spends three VALU instructions:
+//    single column sequence, so the column symbol is wave-uniform; each lane
+//    reads its row's mask dwords for that symbol from LDS with 128-bit reads
+//    (lane-interleaved layout, conflict free), at an address formed by one
+//    SDWA add from the pre-scaled symbol.  Per 32 cells a lane spends three
+//    VALU instructions:
 //    v_and_b32 (U), v_addc_co_u32 (carry chain through the dwords) and
 //    v_bitop3_b32 (the three-input S | (V & ~M), a gfx950 instruction).
 //    Persistent workgroups pull work items from an atomic queue.
@@ -76,57 +77,41 @@ __global__ void step_begin_kernel(StepCtl* ctl) {
 
 // ------------------------------------------------------------ fast kernel
 
-// LDS table of one 64-row group for W dwords per lane: symbol c occupies
-// W*64 dwords at c*W*64; inside it, dword quad q of lane l is at q*256 + 4l
-// (read with one 128-bit access), a trailing pair at Q*256 + 2l, a trailing
-// single dword at Q*256 + (pair ? 128 : 0) + l.  Consecutive lanes read
-// consecutive 16-, 8- or 4-byte words, so a wave's read is conflict free.
-__device__ __forceinline__ uint32_t lds_index(uint32_t W, uint32_t w, uint32_t lane) {
-  const uint32_t Q = W >> 2, R = W & 3, q = w >> 2;
-  if (q < Q) return q * 256u + lane * 4u + (w & 3u);
-  const uint32_t r = w & 3u;
-  if (R >= 2 && r < 2) return Q * 256u + lane * 2u + r;
-  return Q * 256u + (R >= 2 ? 128u : 0u) + lane;
+// LDS table of one 64-row group: for every dword quad q of the rows' masks
+// (W dwords per lane, Q = ceil(W/4) quads, the last one zero padded) and
+// every symbol c, the 64 lanes' 16-byte quads lie side by side:
+//   byte offset = q * SIG * 1024 + c * 1024 + lane * 16.
+// A wave's 128-bit read of one (q, c) plane is 1 KB of consecutive bytes,
+// conflict free, and the symbol's part c * 1024 does not depend on W, so the
+// column streams store it pre-scaled and one SDWA v_add forms the address.
+template <int SIG>
+__device__ __forceinline__ uint32_t lds_byte(uint32_t q, uint32_t c, uint32_t lane) {
+  return q * (SIG * 1024u) + c * 1024u + lane * 16u;
 }
 
-// One symbol of the column: advance the 32*W-bit vector V of this lane's row.
-template <int W>
-__device__ __forceinline__ void lcs_step(uint32_t (&V)[W], const uint32_t* __restrict__ tab, uint32_t lane) {
-  constexpr int Q = W / 4, R = W % 4;
-  uint32_t M[W];
+// One column symbol: advance this lane's 32*W-bit vector V.  `p` is the
+// lane's address in the symbol's plane of quad 0.
+template <int W, int SIG>
+__device__ __forceinline__ void lcs_step(uint32_t (&V)[W], const char* __restrict__ p) {
+  constexpr int Q = (W + 3) / 4;
+  uint32_t M[4 * Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const uint4 x = *reinterpret_cast<const uint4*>(tab + q * 256 + lane * 4);
+    const uint4 x = *reinterpret_cast<const uint4*>(p + q * (SIG * 1024));
     M[4 * q + 0] = x.x;
     M[4 * q + 1] = x.y;
     M[4 * q + 2] = x.z;
     M[4 * q + 3] = x.w;
   }
-  if constexpr (R >= 2) {
-    const uint2 x = *reinterpret_cast<const uint2*>(tab + Q * 256 + lane * 2);
-    M[4 * Q + 0] = x.x;
-    M[4 * Q + 1] = x.y;
-  }
-  if constexpr (R & 1) M[W - 1] = tab[Q * 256 + (R >= 2 ? 128 : 0) + lane];
   uint32_t c = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const uint32_t U = V[w] & M[w];
     uint32_t co;
     const uint32_t S = __builtin_addc(V[w], U, c, &co);
-    c = co;  // carry out of the top dword is dropped: it leaves the row
+    c = co;  // the carry out of the top dword leaves the row
     V[w] = __builtin_amdgcn_bitop3_b32(S, V[w], M[w], 0xF4);  // S | (V & ~M)
   }
-}
-
-template <int W>
-__device__ __forceinline__ void lcs_step4(uint32_t (&V)[W], const uint32_t* __restrict__ lds, uint32_t lane,
-                                          uint32_t word) {
-  constexpr uint32_t kSym = W * 64;
-  lcs_step<W>(V, lds + (word & 0xFFu) * kSym, lane);
-  lcs_step<W>(V, lds + ((word >> 8) & 0xFFu) * kSym, lane);
-  lcs_step<W>(V, lds + ((word >> 16) & 0xFFu) * kSym, lane);
-  lcs_step<W>(V, lds + (word >> 24) * kSym, lane);
 }
 
 struct LaneCtx {
@@ -135,15 +120,19 @@ struct LaneCtx {
 };
 
 // All columns of one work item for a group with W dwords per lane.  Waves
-// take columns from a shared LDS counter so they stay balanced.
-template <int W>
-__device__ __forceinline__ void run_item(const uint8_t* __restrict__ codes, const uint64_t* __restrict__ dev_off,
-                                         const uint32_t* __restrict__ len, const uint32_t* __restrict__ colmap,
+// take columns from a shared LDS counter so they stay balanced.  The column
+// stream is read with vector loads at a wave-uniform address (kept in VGPRs,
+// counted by vmcnt, so waiting for it never waits for the LDS reads), one
+// 8-symbol chunk ahead of use.
+template <int W, int SIG>
+__device__ __forceinline__ void run_item(const DeviceBatch& bt, const uint32_t* __restrict__ colmap,
                                          const uint64_t* __restrict__ rowbase, const GroupDesc& g, uint32_t c1,
-                                         const uint32_t* __restrict__ lds, uint32_t* s_col, const LaneCtx& lc,
+                                         const char* __restrict__ lds, uint32_t* s_col, const LaneCtx& lc,
                                          int32_t* __restrict__ out) {
-  constexpr uint32_t kSym = W * 64;
   const uint32_t lane = threadIdx.x & 63u;
+  const char* lbase = lds + lane * 16u;
+  uint32_t vzero;  // a zero the compiler must treat as per-lane: keeps the stream loads in VGPRs
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
   for (;;) {
     uint32_t col = 0;
     if (lane == 0) col = atomicAdd(s_col, 1u);
@@ -152,26 +141,31 @@ __device__ __forceinline__ void run_item(const uint8_t* __restrict__ codes, cons
     const uint32_t b = g.colmap_base == kNoMap ? col : colmap[g.colmap_base + col];
     const uint64_t rb = g.rowbase_base == kNoMap ? 0ull : rowbase[g.rowbase_base + b];
     const uint32_t s = g.fam_base + b;
-    const uint32_t n = len[s];
-    const uint4* B = reinterpret_cast<const uint4*>(codes + dev_off[s]);
+    const uint32_t n = bt.len[s];
+    const uint4* B = reinterpret_cast<const uint4*>(bt.sym + bt.sym_off[s]) + vzero;
     uint32_t V[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) V[w] = 0xFFFFFFFFu;
-    const uint32_t nch = n >> 4;
+    const uint32_t nch = n >> 3;
+    uint4 nxt = B[0];
     for (uint32_t ch = 0; ch < nch; ++ch) {
-      const uint4 q = B[ch];
-      lcs_step4<W>(V, lds, lane, q.x);
-      lcs_step4<W>(V, lds, lane, q.y);
-      lcs_step4<W>(V, lds, lane, q.z);
-      lcs_step4<W>(V, lds, lane, q.w);
+      const uint4 q = nxt;
+      nxt = B[ch + 1];  // the spare chunk makes this read safe on the last chunk
+      lcs_step<W, SIG>(V, lbase + (q.x & 0xFFFFu));
+      lcs_step<W, SIG>(V, lbase + (q.x >> 16));
+      lcs_step<W, SIG>(V, lbase + (q.y & 0xFFFFu));
+      lcs_step<W, SIG>(V, lbase + (q.y >> 16));
+      lcs_step<W, SIG>(V, lbase + (q.z & 0xFFFFu));
+      lcs_step<W, SIG>(V, lbase + (q.z >> 16));
+      lcs_step<W, SIG>(V, lbase + (q.w & 0xFFFFu));
+      lcs_step<W, SIG>(V, lbase + (q.w >> 16));
     }
-    const uint32_t rem = n & 15u;
+    const uint32_t rem = n & 7u;
     if (rem) {
-      const uint4 q = B[nch];  // inside the 32-byte padding of the sequence
-      for (uint32_t t = 0; t < rem; ++t) {
-        const uint32_t word = t < 4 ? q.x : (t < 8 ? q.y : (t < 12 ? q.z : q.w));
-        const uint32_t sym = (word >> (8u * (t & 3u))) & 0xFFu;
-        lcs_step<W>(V, lds + sym * kSym, lane);
+      const uint32_t qw[4] = {nxt.x, nxt.y, nxt.z, nxt.w};
+#pragma unroll
+      for (uint32_t t = 0; t < 7; ++t) {
+        if (t < rem) lcs_step<W, SIG>(V, lbase + ((qw[t >> 1] >> (16u * (t & 1u))) & 0xFFFFu));
       }
     }
     uint32_t cnt = 0;
@@ -184,31 +178,29 @@ __device__ __forceinline__ void run_item(const uint8_t* __restrict__ codes, cons
   }
 }
 
-template <int W, int WHI>
-__device__ __forceinline__ void dispatch_w(uint32_t w, const uint8_t* __restrict__ codes,
-                                           const uint64_t* __restrict__ dev_off, const uint32_t* __restrict__ len,
-                                           const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase,
-                                           const GroupDesc& g, uint32_t c1, const uint32_t* __restrict__ lds,
-                                           uint32_t* s_col, const LaneCtx& lc, int32_t* __restrict__ out) {
+template <int W, int WHI, int SIG>
+__device__ __forceinline__ void dispatch_w(uint32_t w, const DeviceBatch& bt, const uint32_t* __restrict__ colmap,
+                                           const uint64_t* __restrict__ rowbase, const GroupDesc& g, uint32_t c1,
+                                           const char* __restrict__ lds, uint32_t* s_col, const LaneCtx& lc,
+                                           int32_t* __restrict__ out) {
   if constexpr (W <= WHI) {
     if (w == W) {
-      run_item<W>(codes, dev_off, len, colmap, rowbase, g, c1, lds, s_col, lc, out);
+      run_item<W, SIG>(bt, colmap, rowbase, g, c1, lds, s_col, lc, out);
       return;
     }
-    dispatch_w<W + 1, WHI>(w, codes, dev_off, len, colmap, rowbase, g, c1, lds, s_col, lc, out);
+    dispatch_w<W + 1, WHI, SIG>(w, bt, colmap, rowbase, g, c1, lds, s_col, lc, out);
   }
 }
 
-template <int CLS>
+template <int CLS, int SIG>
 __global__ __launch_bounds__(1024) void lcs_fast_kernel(
-    const uint8_t* __restrict__ codes, const uint64_t* __restrict__ dev_off, const uint32_t* __restrict__ len,
-    const uint64_t* __restrict__ mask_off, const uint32_t* __restrict__ masks,
-    const GroupDesc* __restrict__ groups, const LaneDesc* __restrict__ lanes, const ItemDesc* __restrict__ items,
-    const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase, const StepRange* __restrict__ ranges,
-    StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint32_t sigma) {
-  constexpr int WLO = CLS == 0 ? 1 : kClassWMax[CLS - 1] + 1;
-  constexpr int WHI = kClassWMax[CLS];
-  extern __shared__ uint32_t lds[];
+    DeviceBatch bt, const GroupDesc* __restrict__ groups, const LaneDesc* __restrict__ lanes,
+    const ItemDesc* __restrict__ items, const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase,
+    const StepRange* __restrict__ ranges, StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint32_t sigma) {
+  constexpr int WLO = CLS == 0 ? 1 : 4 * kClassQMax[CLS > 0 ? CLS - 1 : 0] + 1;
+  constexpr int WHI = 4 * kClassQMax[CLS];
+  extern __shared__ uint4 lds4[];
+  char* lds = reinterpret_cast<char*>(lds4);
   __shared__ uint32_t s_item;
   __shared__ uint32_t s_col;
   const uint32_t step = ctl->step;
@@ -233,21 +225,204 @@ __global__ __launch_bounds__(1024) void lcs_fast_kernel(
       lc.orig = d.orig;
       seq = d.seq;
     }
-    {  // stage the group's masks in LDS (zero past each row's end)
-      const uint32_t W = g.W;
-      const uint32_t Ws = lane < g.nrows ? (len[seq] + 31u) >> 5 : 0u;
-      const uint64_t mo = lane < g.nrows ? mask_off[seq] : 0ull;
-      const uint32_t n = sigma * W;
+    {  // stage the group's masks in LDS (zero past each row's end and in the padding)
+      const uint32_t Q = (g.W + 3u) >> 2;
+      const uint32_t Ws = lane < g.nrows ? (bt.len[seq] + 31u) >> 5 : 0u;
+      const uint64_t mo = lane < g.nrows ? bt.mask_off[seq] : 0ull;
+      const uint32_t n = Q * sigma;
       for (uint32_t e = wave; e < n; e += nwaves) {
-        const uint32_t c = e / W, w = e - c * W;
-        const uint32_t v = (w < Ws) ? masks[mo + (uint64_t)c * Ws + w] : 0u;
-        lds[c * W * 64u + lds_index(W, w, lane)] = v;
+        const uint32_t q = e / sigma, c = e - q * sigma;
+        uint4 v;
+        const uint32_t w0 = 4u * q;
+        const uint32_t* src = bt.masks + mo + (uint64_t)c * Ws;
+        v.x = w0 + 0 < Ws ? src[w0 + 0] : 0u;
+        v.y = w0 + 1 < Ws ? src[w0 + 1] : 0u;
+        v.z = w0 + 2 < Ws ? src[w0 + 2] : 0u;
+        v.w = w0 + 3 < Ws ? src[w0 + 3] : 0u;
+        *reinterpret_cast<uint4*>(lds + lds_byte<SIG>(q, c, lane)) = v;
       }
     }
     if (threadIdx.x == 0) s_col = item.c0;
     __syncthreads();
-    dispatch_w<WLO, WHI>(g.W, codes, dev_off, len, colmap, rowbase, g, item.c1, lds, &s_col, lc, out);
+    dispatch_w<WLO, WHI, SIG>(g.W, bt, colmap, rowbase, g, item.c1, lds, &s_col, lc, out);
     __syncthreads();  // LDS and s_item are reused by the next item
+  }
+}
+
+// ------------------------------------------------------------ long rows
+
+// One segment of W dwords of a long row against a whole column.  Carries
+// between segments travel as one bit per column step: the segment below
+// wrote the carry out of its top dword at step t into bit 31 - (t mod 32) of
+// word t / 32 of this lane's carry row; this segment consumes it as its own
+// carry in and, unless it is the top segment, writes its own carry out the
+// same way.  `crow` points at the lane's dword for block 0; blocks are 64
+// dwords apart (one per lane), so a wave's carry traffic is coalesced.
+template <int W, int SIG>
+__device__ __forceinline__ void long_step(uint32_t (&V)[W], const char* __restrict__ p, uint32_t& cin, uint32_t& cout) {
+  constexpr int Q = (W + 3) / 4;
+  uint32_t M[4 * Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p + q * (SIG * 1024));
+    M[4 * q + 0] = x.x;
+    M[4 * q + 1] = x.y;
+    M[4 * q + 2] = x.z;
+    M[4 * q + 3] = x.w;
+  }
+  uint32_t c;
+  cin = __builtin_addc(cin, cin, 0u, &c);  // c = this step's carry in (the top bit); shift it out
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t U = V[w] & M[w];
+    uint32_t co;
+    const uint32_t S = __builtin_addc(V[w], U, c, &co);
+    c = co;
+    V[w] = __builtin_amdgcn_bitop3_b32(S, V[w], M[w], 0xF4);
+  }
+  uint32_t dummy;
+  cout = __builtin_addc(cout, cout, c, &dummy);  // append this step's carry out
+}
+
+template <int W, int SIG>
+__device__ __forceinline__ uint32_t long_segment(const uint4* __restrict__ B, uint32_t n, const char* __restrict__ lbase,
+                                                 uint32_t* __restrict__ crow, bool has_in, bool has_out) {
+  uint32_t V[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) V[w] = 0xFFFFFFFFu;
+  const uint32_t nch = n >> 3, rem = n & 7u;
+  uint32_t cin = 0, cout = 0;
+  uint4 nxt = B[0];
+  for (uint32_t ch = 0; ch < nch; ++ch) {
+    if ((ch & 3u) == 0 && has_in) cin = crow[(uint64_t)(ch >> 2) * 64];
+    const uint4 q = nxt;
+    nxt = B[ch + 1];  // the spare chunk makes this read safe on the last chunk
+    long_step<W, SIG>(V, lbase + (q.x & 0xFFFFu), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.x >> 16), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.y & 0xFFFFu), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.y >> 16), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.z & 0xFFFFu), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.z >> 16), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.w & 0xFFFFu), cin, cout);
+    long_step<W, SIG>(V, lbase + (q.w >> 16), cin, cout);
+    if ((ch & 3u) == 3u) {  // 32 steps: step 32*blk at bit 31
+      if (has_out) crow[(uint64_t)(ch >> 2) * 64] = cout;
+      cout = 0;
+    }
+  }
+  if (rem) {
+    if ((nch & 3u) == 0 && has_in) cin = crow[(uint64_t)(nch >> 2) * 64];
+    const uint32_t qw[4] = {nxt.x, nxt.y, nxt.z, nxt.w};
+#pragma unroll
+    for (uint32_t t = 0; t < 7; ++t)
+      if (t < rem) long_step<W, SIG>(V, lbase + ((qw[t >> 1] >> (16u * (t & 1u))) & 0xFFFFu), cin, cout);
+  }
+  const uint32_t tn = (nch & 3u) * 8u + rem;  // steps of the last, partial 32-step block
+  if (has_out && tn) crow[(uint64_t)(nch >> 2) * 64] = cout << (32u - tn);
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) cnt += __builtin_popcount(~V[w]);
+  return cnt;
+}
+
+template <int W, int WHI, int SIG>
+__device__ __forceinline__ uint32_t long_segment_w(uint32_t w, const uint4* __restrict__ B, uint32_t n,
+                                                   const char* __restrict__ lbase, uint32_t* __restrict__ crow,
+                                                   bool has_in, bool has_out) {
+  if constexpr (W <= WHI) {
+    if (w == W) return long_segment<W, SIG>(B, n, lbase, crow, has_in, has_out);
+    return long_segment_w<W + 1, WHI, SIG>(w, B, n, lbase, crow, has_in, has_out);
+  } else {
+    return 0;
+  }
+}
+
+// Rows whose bit vectors exceed the fast classes.  A workgroup takes a work
+// item (group, columns); its waves take one column each per pass, and for
+// every segment of the rows (SEGQ quads) the workgroup stages that segment's
+// masks in LDS and all waves run it over their columns.  Columns of a pass
+// are neighbours in length order (family mode), so the barriers between
+// segments cost little.
+template <int SEGQ, int SIG>
+__global__ __launch_bounds__(1024) void lcs_long_kernel(
+    DeviceBatch bt, const GroupDesc* __restrict__ groups, const LaneDesc* __restrict__ lanes,
+    const ItemDesc* __restrict__ items, const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase,
+    const StepRange* __restrict__ ranges, StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint32_t sigma,
+    uint32_t* __restrict__ carry, uint32_t carry_words) {
+  constexpr uint32_t SEGW = 4 * SEGQ;
+  extern __shared__ uint4 lds4[];
+  char* lds = reinterpret_cast<char*>(lds4);
+  __shared__ uint32_t s_item;
+  const uint32_t step = ctl->step;
+  const uint32_t begin = ranges[step].begin[3];
+  const uint32_t end = ranges[step].end[3];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t nwaves = blockDim.x >> 6;
+  uint32_t* crow = carry + ((uint64_t)(blockIdx.x * nwaves + wave) * carry_words) * 64u + lane;
+  const char* lbase = lds + lane * 16u;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = begin + atomicAdd(&ctl->cursor[3], 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    __syncthreads();  // everyone has read s_item before it can change
+    if (it >= end) break;
+    const ItemDesc item = items[it];
+    const GroupDesc g = groups[item.group];
+    uint32_t pos = 0xFFFFFFFFu, orig = 0, seq = 0;
+    uint64_t out_off = 0;
+    if (lane < g.nrows) {
+      const LaneDesc d = lanes[g.lane_first + lane];
+      out_off = d.out_off;
+      pos = d.pos;
+      orig = d.orig;
+      seq = d.seq;
+    }
+    const uint32_t Ws = lane < g.nrows ? (bt.len[seq] + 31u) >> 5 : 0u;
+    const uint64_t mo = lane < g.nrows ? bt.mask_off[seq] : 0ull;
+    const uint32_t nseg = (g.W + SEGW - 1) / SEGW;
+    for (uint32_t cb = item.c0; cb < item.c1; cb += nwaves) {
+      const uint32_t col = cb + wave;
+      const bool valid = col < item.c1;
+      uint32_t b = 0, n = 0;
+      uint64_t rb = 0;
+      const uint4* B = nullptr;
+      if (valid) {
+        b = g.colmap_base == kNoMap ? col : colmap[g.colmap_base + col];
+        rb = g.rowbase_base == kNoMap ? 0ull : rowbase[g.rowbase_base + b];
+        const uint32_t s = g.fam_base + b;
+        n = bt.len[s];
+        B = reinterpret_cast<const uint4*>(bt.sym + bt.sym_off[s]);
+      }
+      uint32_t cnt = 0;
+      for (uint32_t sg = 0; sg < nseg; ++sg) {
+        __syncthreads();  // the previous segment's LDS reads are done
+        const uint32_t wbase = sg * SEGW;
+        const uint32_t segw = min(SEGW, g.W - wbase);
+        const uint32_t qn = (segw + 3u) >> 2;
+        for (uint32_t e = wave; e < qn * sigma; e += nwaves) {
+          const uint32_t q = e / sigma, c = e - q * sigma;
+          const uint32_t w0 = wbase + 4u * q;
+          const uint32_t* src = bt.masks + mo + (uint64_t)c * Ws;
+          uint4 v;
+          v.x = w0 + 0 < Ws ? src[w0 + 0] : 0u;
+          v.y = w0 + 1 < Ws ? src[w0 + 1] : 0u;
+          v.z = w0 + 2 < Ws ? src[w0 + 2] : 0u;
+          v.w = w0 + 3 < Ws ? src[w0 + 3] : 0u;
+          *reinterpret_cast<uint4*>(lds + lds_byte<SIG>(q, c, lane)) = v;
+        }
+        __syncthreads();
+        if (valid) {
+          const bool has_in = sg > 0, has_out = sg + 1 < nseg;
+          if (segw == SEGW) cnt += long_segment<SEGW, SIG>(B, n, lbase, crow, has_in, has_out);
+          else cnt += long_segment_w<1, SEGW, SIG>(segw, B, n, lbase, crow, has_in, has_out);
+        }
+      }
+      if (valid && col > pos) {
+        const uint64_t o = orig < b ? out_off + (b - orig - 1u) : rb + (orig - b - 1u);
+        out[o] = (int32_t)cnt;
+      }
+    }
   }
 }
 
@@ -263,7 +438,7 @@ __global__ __launch_bounds__(256) void lcs_plain_kernel(
     const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase, const StepRange* __restrict__ ranges,
     const StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint64_t* __restrict__ work) {
   const uint32_t step = ctl->step;
-  const uint32_t rb = ranges[step].begin[3], re = ranges[step].end[3];
+  const uint32_t rb = ranges[step].begin[4], re = ranges[step].end[4];
   const uint64_t total = ranges[step].plain_pairs;
   const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -351,52 +526,90 @@ int launch_step_begin(StepCtl* ctl, void* stream) {
   return hip_ok(hipGetLastError());
 }
 
-size_t fast_lds_bytes(uint32_t sigma, uint32_t wmax) { return (size_t)sigma * wmax * 64u * 4u; }
-
-template <int CLS>
+template <int CLS, int SIG>
 static const void* fast_fn() {
-  return reinterpret_cast<const void*>(&lcs_fast_kernel<CLS>);
+  return reinterpret_cast<const void*>(&lcs_fast_kernel<CLS, SIG>);
 }
 
-static const void* fast_kernel_ptr(int cls) {
+static const void* fast_kernel_ptr(int cls, uint32_t sigma) {
+  const bool small = sig_cap(sigma) == 20;
   switch (cls) {
-    case 0: return fast_fn<0>();
-    case 1: return fast_fn<1>();
-    default: return fast_fn<2>();
+    case 0: return small ? fast_fn<0, 20>() : fast_fn<0, 32>();
+    case 1: return small ? fast_fn<1, 20>() : fast_fn<1, 32>();
+    default: return small ? fast_fn<2, 20>() : fast_fn<2, 32>();
   }
 }
 
 // Allow the class's dynamic LDS and report how many workgroups of `waves`
 // waves fit on one CU.  Call before any launch (and before graph capture).
-int fast_prepare(int cls, uint32_t sigma, uint32_t wmax, uint32_t waves, int* blocks_per_cu) {
-  const size_t lds = fast_lds_bytes(sigma, wmax);
+int fast_prepare(int cls, uint32_t sigma, uint32_t qmax, uint32_t waves, int* blocks_per_cu) {
+  const size_t lds = fast_lds_bytes(sigma, qmax);
+  const void* fn = fast_kernel_ptr(cls, sigma);
   hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, fast_kernel_ptr(cls));
+  hipError_t e = hipFuncGetAttributes(&fa, fn);
   if (e != hipSuccess) return (int)e;
   if (fa.sharedSizeBytes > kLdsReserve || lds + kLdsReserve > g_max_lds) return (int)hipErrorInvalidValue;
-  e = hipFuncSetAttribute(fast_kernel_ptr(cls), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(g_max_lds - fa.sharedSizeBytes));
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(g_max_lds - fa.sharedSizeBytes));
   if (e != hipSuccess) return (int)e;
   int nb = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fast_kernel_ptr(cls), (int)(waves * 64), lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)(waves * 64), lds);
   if (e != hipSuccess) return (int)e;
   if (blocks_per_cu) *blocks_per_cu = nb;
   return 0;
 }
 
 int launch_fast(int cls, const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint32_t sigma,
-                uint32_t wmax, uint32_t blocks, uint32_t waves, void* stream) {
-  const size_t lds = fast_lds_bytes(sigma, wmax);
+                uint32_t qmax, uint32_t blocks, uint32_t waves, void* stream) {
+  const size_t lds = fast_lds_bytes(sigma, qmax);
   const dim3 grid(blocks), block(waves * 64);
-#define FAMSA_FAST(C)                                                                                            \
-  hipLaunchKernelGGL(lcs_fast_kernel<C>, grid, block, lds, (hipStream_t)stream, b.codes, b.dev_off, b.len,        \
-                     b.mask_off, b.masks, w.groups, w.lanes, w.items, w.colmap, w.rowbase, w.ranges, ctl, out, sigma)
+  const bool small = sig_cap(sigma) == 20;
+#define FAMSA_FAST(C, S)                                                                                       \
+  hipLaunchKernelGGL((lcs_fast_kernel<C, S>), grid, block, lds, (hipStream_t)stream, b, w.groups, w.lanes,     \
+                     w.items, w.colmap, w.rowbase, w.ranges, ctl, out, sigma)
   switch (cls) {
-    case 0: FAMSA_FAST(0); break;
-    case 1: FAMSA_FAST(1); break;
-    default: FAMSA_FAST(2); break;
+    case 0: if (small) FAMSA_FAST(0, 20); else FAMSA_FAST(0, 32); break;
+    case 1: if (small) FAMSA_FAST(1, 20); else FAMSA_FAST(1, 32); break;
+    default: if (small) FAMSA_FAST(2, 20); else FAMSA_FAST(2, 32); break;
   }
 #undef FAMSA_FAST
+  return hip_ok(hipGetLastError());
+}
+
+template <int SQ, int SIG>
+static const void* long_fn() {
+  return reinterpret_cast<const void*>(&lcs_long_kernel<SQ, SIG>);
+}
+
+static const void* long_kernel_ptr(uint32_t sigma) {
+  return sig_cap(sigma) == 20 ? long_fn<kLongSegQ[0], 20>() : long_fn<kLongSegQ[1], 32>();
+}
+
+int long_prepare(uint32_t sigma, uint32_t waves, int* blocks_per_cu) {
+  const size_t lds = fast_lds_bytes(sigma, long_seg_q(sigma));
+  const void* fn = long_kernel_ptr(sigma);
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, fn);
+  if (e != hipSuccess) return (int)e;
+  if (fa.sharedSizeBytes > kLdsReserve || lds + kLdsReserve > g_max_lds) return (int)hipErrorInvalidValue;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(g_max_lds - fa.sharedSizeBytes));
+  if (e != hipSuccess) return (int)e;
+  int nb = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)(waves * 64), lds);
+  if (e != hipSuccess) return (int)e;
+  if (blocks_per_cu) *blocks_per_cu = nb;
+  return 0;
+}
+
+int launch_long(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint32_t sigma,
+                uint32_t* carry, uint32_t carry_words, uint32_t blocks, uint32_t waves, void* stream) {
+  const size_t lds = fast_lds_bytes(sigma, long_seg_q(sigma));
+  const dim3 grid(blocks), block(waves * 64);
+  if (sig_cap(sigma) == 20)
+    hipLaunchKernelGGL((lcs_long_kernel<kLongSegQ[0], 20>), grid, block, lds, (hipStream_t)stream, b, w.groups,
+                       w.lanes, w.items, w.colmap, w.rowbase, w.ranges, ctl, out, sigma, carry, carry_words);
+  else
+    hipLaunchKernelGGL((lcs_long_kernel<kLongSegQ[1], 32>), grid, block, lds, (hipStream_t)stream, b, w.groups,
+                       w.lanes, w.items, w.colmap, w.rowbase, w.ranges, ctl, out, sigma, carry, carry_words);
   return hip_ok(hipGetLastError());
 }
 

@@ -42,13 +42,14 @@ struct famsa_lcs_plan_s {
   StepExec exec;
   DevMem d_groups, d_lanes, d_items, d_prows, d_colmap, d_rowbase, d_ranges, d_ctl;
   DevMem d_plainwork[2];  // per compute stream: steps on the two streams run concurrently
+  DevMem d_carry[2];      // long-row carry scratch, per compute stream
   DevMem d_out[2];
   PinMem h_out[2];
   uint64_t step_cap = 0;  // values per step buffer
   hipStream_t cs[2] = {nullptr, nullptr};
   hipStream_t xs = nullptr;
   hipEvent_t ev_comp[2] = {}, ev_copy[2] = {}, ev_s0[2] = {}, ev_s1[2] = {}, ev_user = nullptr;
-  hipEvent_t ev_k[2][8] = {};
+  hipEvent_t ev_k[2][10] = {};
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   std::atomic<int> busy{0};
   famsa_lcs_stats stats{};
@@ -86,7 +87,7 @@ famsa_lcs_plan_s::~famsa_lcs_plan_s() {
     if (ev_copy[i]) (void)hipEventDestroy(ev_copy[i]);
     if (ev_s0[i]) (void)hipEventDestroy(ev_s0[i]);
     if (ev_s1[i]) (void)hipEventDestroy(ev_s1[i]);
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < 10; ++j)
       if (ev_k[i][j]) (void)hipEventDestroy(ev_k[i][j]);
     if (cs[i]) (void)hipStreamDestroy(cs[i]);
   }
@@ -168,7 +169,7 @@ int famsa_lcs_plan_s::host_phase(const uint64_t* seq_off, uint32_t nseq) {
     const uint64_t k = fam_off[f + 1] - fam_off[f];
     pairs += k * (k ? k - 1 : 0) / 2;
   }
-  for (int c = 0; c < 4; ++c) cells += wl.cells[c];
+  for (int c = 0; c < 5; ++c) cells += wl.cells[c];
   return 0;
 }
 
@@ -199,7 +200,7 @@ int famsa_lcs_plan_s::setup_device() {
     FAMSA_HIP(hipEventCreateWithFlags(&ev_copy[i], hipEventDisableTiming));
     FAMSA_HIP(hipEventCreate(&ev_s0[i]));
     FAMSA_HIP(hipEventCreate(&ev_s1[i]));
-    for (int j = 0; j < 8; ++j) FAMSA_HIP(hipEventCreate(&ev_k[i][j]));
+    for (int j = 0; j < 10; ++j) FAMSA_HIP(hipEventCreate(&ev_k[i][j]));
   }
   FAMSA_HIP(hipEventCreateWithFlags(&ev_user, hipEventDisableTiming));
   return 0;
@@ -211,8 +212,8 @@ int famsa_lcs_plan_s::capture_graphs() {
   for (int slot = 0; slot < 2; ++slot) {
     hipGraph_t g = nullptr;
     FAMSA_HIP(hipStreamBeginCapture(cs[slot], hipStreamCaptureModeThreadLocal));
-    int rc = exec.enqueue(b, w, ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(), cs[slot],
-                          nullptr);
+    int rc = exec.enqueue(b, w, ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(),
+                          d_carry[slot].as<uint32_t>(), cs[slot], nullptr);
     hipError_t e = hipStreamEndCapture(cs[slot], &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
@@ -233,8 +234,8 @@ int famsa_lcs_plan_s::enqueue_step(uint64_t s, int slot, bool timed) {
   if (use_graph()) {
     FAMSA_HIP(hipGraphLaunch(graph[slot], st));
   } else {
-    int rc = exec.enqueue(batch.view(), work(), ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(), st,
-                          timed ? ev_k[slot] : nullptr);
+    int rc = exec.enqueue(batch.view(), work(), ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(),
+                          d_carry[slot].as<uint32_t>(), st, timed ? ev_k[slot] : nullptr);
     if (rc) return rc;
   }
   FAMSA_HIP(hipEventRecord(ev_s1[slot], st));
@@ -291,12 +292,12 @@ int famsa_lcs_plan_s::autotune(const char* path) {
                        tr.as<uint64_t>(), tra.as<StepRange>()};
     double total = 0;
     for (int c = 0; c < 3; ++c) {
-      if (!w1.wmax[c]) continue;
+      if (!w1.qmax[c]) continue;
       double bc = 1e300;
       uint32_t bw = cand.waves[c];
       for (uint32_t wv : kWaves[c]) {
         int bpc = 0;
-        if (fast_prepare(c, opt.sigma, w1.wmax[c], wv, &bpc) || bpc == 0) continue;
+        if (fast_prepare(c, opt.sigma, w1.qmax[c], wv, &bpc) || bpc == 0) continue;
         StepCtl hc{};
         hc.next_step = 0;
         hc.stride = 1;
@@ -305,7 +306,7 @@ int famsa_lcs_plan_s::autotune(const char* path) {
           FAMSA_HIP(hipMemcpyAsync(d_ctl.p, &hc, sizeof hc, hipMemcpyHostToDevice, st));
           if (launch_step_begin(ctl(0), st)) return set_error(FAMSA_LCS_EDEVICE, "step_begin failed");
           FAMSA_HIP(hipEventRecord(e0, st));
-          if (launch_fast(c, batch.view(), w, ctl(0), d_out[0].as<int32_t>(), opt.sigma, w1.wmax[c],
+          if (launch_fast(c, batch.view(), w, ctl(0), d_out[0].as<int32_t>(), opt.sigma, w1.qmax[c],
                           (uint32_t)(bpc * gi.cus), wv, st))
             return set_error(FAMSA_LCS_EDEVICE, "tuning launch failed");
           FAMSA_HIP(hipEventRecord(e1, st));
@@ -342,6 +343,9 @@ int famsa_lcs_plan_s::autotune(const char* path) {
   if ((rc = exec.prepare(gi.cus, lp, wl, opt.sigma))) return rc;
   if (exec.w64max_plain > plain_register_w64_limit())
     exec.plain_blocks = std::min<uint32_t>(exec.plain_blocks, (uint32_t)gi.cus * 8u);
+  for (int i = 0; i < 2; ++i)
+    if (exec.has_long && d_carry[i].bytes < exec.carry_bytes() && (rc = d_carry[i].alloc(exec.carry_bytes())))
+      return rc;
   if (use_graph() && (rc = capture_graphs())) return rc;
   return 0;
 }
@@ -406,9 +410,9 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
     if (hipEventElapsedTime(&stepms, ev_s0[slot], ev_s1[slot]) == hipSuccess) stats.step_ms += stepms;
     stats.steps++;
     if (timed) {
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < 5; ++c) {
         float km = 0.f;
-        if ((c < 3 ? exec.wmax[c] != 0 : exec.plain_blocks != 0) &&
+        if ((c < 3 ? exec.qmax[c] != 0 : c == 3 ? exec.has_long : exec.plain_blocks != 0) &&
             hipEventElapsedTime(&km, ev_k[slot][2 * c], ev_k[slot][2 * c + 1]) == hipSuccess) {
           stats.kernel_ms[c] += km;
           stats.launches[c] += 1;
@@ -439,7 +443,7 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
     return rc;
   }
   stats.wall_ms = ms_since(t0);
-  for (int c = 0; c < 4; ++c) stats.cells[c] = wl.cells[c];
+  for (int c = 0; c < 5; ++c) stats.cells[c] = wl.cells[c];
   if (opt.user_stream) {
     for (int i = 0; i < 2; ++i) {
       FAMSA_HIP(hipEventRecord(ev_comp[i], cs[i]));
@@ -529,6 +533,9 @@ int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
                                                                       (p->wl.max_plain_pairs + kPlainBlock - 1) / kPlainBlock,
                                                                       1u << 20)
                                                                 : 0;
+  if (p->exec.has_long)
+    for (int i = 0; i < nbuf; ++i)
+      if ((rc = p->d_carry[i].alloc(p->exec.carry_bytes()))) return fail(rc);
   if (p->exec.w64max_plain > plain_register_w64_limit()) {
     p->exec.plain_blocks = std::min<uint32_t>(p->exec.plain_blocks, (uint32_t)p->gi.cus * 8u);
     const uint64_t thr = (uint64_t)p->exec.plain_blocks * kPlainBlock;
@@ -599,13 +606,13 @@ int famsa_lcs_plan_get_info(const famsa_lcs_plan_t* p, famsa_lcs_plan_info* info
   info->cells = p->cells;
   info->device_bytes = p->batch.bytes + p->d_groups.bytes + p->d_lanes.bytes + p->d_items.bytes + p->d_prows.bytes +
                        p->d_colmap.bytes + p->d_rowbase.bytes + p->d_ranges.bytes + p->d_ctl.bytes +
-                       p->d_plainwork[0].bytes + p->d_plainwork[1].bytes + p->d_out[0].bytes + p->d_out[1].bytes;
+                       p->d_plainwork[0].bytes + p->d_plainwork[1].bytes + p->d_carry[0].bytes + p->d_carry[1].bytes + p->d_out[0].bytes + p->d_out[1].bytes;
   info->pinned_bytes = p->h_out[0].bytes + p->h_out[1].bytes;
   for (const auto& t : p->tiles) info->max_tile_values = std::max(info->max_tile_values, t.count);
   info->nfam = (uint32_t)p->fam_off.size() - 1;
   info->max_len = p->batch.max_len;
   info->cols_per_item = p->lp.cols_per_item;
-  for (int c = 0; c < 3; ++c) info->waves_per_group[c] = p->exec.waves[c];
+  for (int c = 0; c < 4; ++c) info->waves_per_group[c] = p->exec.waves[c];
   return 0;
 }
 

@@ -134,8 +134,8 @@ int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
 }
 
 DeviceBatch DeviceBatchOwner::view() const {
-  return DeviceBatch{codes.as<uint8_t>(), dev_off.as<uint64_t>(), len.as<uint32_t>(), mask_off.as<uint64_t>(),
-                     masks.as<uint32_t>()};
+  return DeviceBatch{codes.as<uint8_t>(), dev_off.as<uint64_t>(), sym.as<uint8_t>(), sym_off.as<uint64_t>(),
+                     len.as<uint32_t>(),       mask_off.as<uint64_t>(), masks.as<uint32_t>()};
 }
 
 static inline uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -147,7 +147,9 @@ uint64_t DeviceBatchOwner::footprint(const uint64_t* seq_off, uint32_t nseq, uin
     cb += round_up(L, kSeqAlign);
     words += (L + 31) / 32;
   }
-  return cb + 32 + (uint64_t)nseq * (8 + 4 + 8 + 8) + 16 + words * sigma * 4;
+  uint64_t sb = 0;
+  for (uint32_t i = 0; i < nseq; ++i) sb += ((seq_off[i + 1] - seq_off[i] + 7) / 8 + 1) * 16;
+  return cb + 32 + sb + (uint64_t)nseq * (8 + 8 + 4 + 8 + 8) + 16 + words * sigma * 4;
 }
 
 int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uint32_t n, uint32_t sig,
@@ -178,12 +180,28 @@ int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uin
   std::vector<uint8_t> packed(cb + 32, 0);
   for (uint32_t i = 0; i < n; ++i)
     if (h_len[i]) memcpy(packed.data() + hoff[i], hcodes + seq_off[i], h_len[i]);
+  // column streams: residue c as uint16 c * 1024, ceil(L/8) 16-byte chunks plus one spare
+  h_sym_off.assign(n + 1, 0);
+  uint64_t sb = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    h_sym_off[i] = sb;
+    sb += ((uint64_t)(h_len[i] + 7) / 8 + 1) * 16;
+  }
+  h_sym_off[n] = sb;
+  std::vector<uint16_t> stream(sb / 2, 0);
+  for (uint32_t i = 0; i < n; ++i) {
+    uint16_t* d = stream.data() + h_sym_off[i] / 2;
+    const uint8_t* c = hcodes + seq_off[i];
+    for (uint32_t t = 0; t < h_len[i]; ++t) d[t] = (uint16_t)(c[t] * 1024u);
+  }
   int rc;
   if ((rc = upload(codes, packed, s))) return rc;
   if ((rc = upload(dev_off, hoff, s))) return rc;
   if ((rc = upload(len, h_len, s))) return rc;
   if ((rc = upload(mask_off, hmo, s))) return rc;
   if ((rc = upload(wprefix, hwp, s))) return rc;
+  if ((rc = upload(sym, stream, s))) return rc;
+  if ((rc = upload(sym_off, h_sym_off, s))) return rc;
   if ((rc = masks.alloc(mw * 4 + 16))) return rc;
   h_dev_off = hoff;
   h_mask_off = hmo;
@@ -192,14 +210,16 @@ int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uin
   if (e) return set_error(FAMSA_LCS_EDEVICE, "build_masks launch failed: %s", hipGetErrorString((hipError_t)e));
   // host staging vectors above are freed on return: wait for the copies
   FAMSA_HIP(hipStreamSynchronize(s));
-  bytes = codes.bytes + dev_off.bytes + len.bytes + mask_off.bytes + masks.bytes + wprefix.bytes;
+  bytes = codes.bytes + dev_off.bytes + len.bytes + mask_off.bytes + masks.bytes + wprefix.bytes + sym.bytes +
+          sym_off.bytes;
   return 0;
 }
 
 int class_of(uint32_t W, uint32_t sigma) {
-  if (fast_lds_bytes(sigma, W) + kLdsReserve > g_max_lds) return 3;
+  const uint32_t Q = (W + 3) / 4;
+  if (fast_lds_bytes(sigma, Q) + kLdsReserve > g_max_lds) return 3;
   for (int c = 0; c < 3; ++c)
-    if (W <= (uint32_t)kClassWMax[c]) return c;
+    if (Q <= (uint32_t)kClassQMax[c]) return c;
   return 3;
 }
 
@@ -213,7 +233,7 @@ struct CostItem {
 void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::vector<uint32_t>& len,
                 const std::vector<uint64_t>& lenprefix, uint32_t sigma, const LaunchParams& lp, bool plain_only) {
   StepRange r{};
-  std::vector<CostItem> ci[3];
+  std::vector<CostItem> ci[4];
   std::vector<PlainRow> pr;
   uint64_t plain_pairs = 0;
 
@@ -272,18 +292,16 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
         g.fam_base = fb;
         g.colmap_base = cm_base;
         g.rowbase_base = rb_base;
-        const int cls = plain_only ? 3 : class_of(W, sigma);
+        const int cls = class_of(W, sigma);
         for (uint32_t l = 0; l < nrows; ++l) {
           const uint32_t a = perm[P + l];
           LaneDesc ld{wl.rowbase[rb_base + a], fb + a, P + l, a, 0};
           wl.cells[cls] += (uint64_t)len[fb + a] * (cp[k] - cp[P + l + 1]);
-          if (cls < 3) wl.lanes.push_back(ld);
-          else add_plain(ld, fb, k, cm_base, rb_base);
+          wl.lanes.push_back(ld);
         }
-        if (cls < 3) {
-          pend.push_back(PendingGroup{g, P + 1, k, cp.data(), 0});
-          span += k - (P + 1);
-        }
+        if (cls == 3) wl.long_col_max = std::max(wl.long_col_max, len[fb + perm[std::min(P + 1, k - 1)]]);
+        pend.push_back(PendingGroup{g, P + 1, k, cp.data(), 0});
+        span += k - (P + 1);
       }
     } else {
       for (const TileWork& t : sf.tiles) {
@@ -308,15 +326,17 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
           g.fam_base = fb;
           g.colmap_base = kNoMap;
           g.rowbase_base = kNoMap;
-          const int cls = plain_only ? 3 : class_of(W, sigma);
+          const int cls = plain_only ? 4 : class_of(W, sigma);
           for (uint32_t l = 0; l < nrows; ++l) {
             const uint32_t i = rows[P + l];
             LaneDesc ld{t.out_off + tri_rows(k, t.r0, i), fb + i, i, i, 0};
             wl.cells[cls] += (uint64_t)len[fb + i] * (lenprefix[fb + k] - lenprefix[fb + i + 1]);
-            if (cls < 3) wl.lanes.push_back(ld);
+            if (cls < 4) wl.lanes.push_back(ld);
             else add_plain(ld, fb, k, kNoMap, kNoMap);
           }
-          if (cls < 3) {
+          if (cls == 3)
+            for (uint32_t j = mini + 1; j < k; ++j) wl.long_col_max = std::max(wl.long_col_max, len[fb + j]);
+          if (cls < 4) {
             pend.push_back(PendingGroup{g, mini + 1, k, nullptr, lenprefix[fb]});
             span += k - (mini + 1);
           }
@@ -334,7 +354,8 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
     const uint32_t gi = (uint32_t)wl.groups.size();
     wl.groups.push_back(pg.g);
     const int cls = class_of(pg.g.W, sigma);
-    wl.wmax[cls] = std::max(wl.wmax[cls], pg.g.W);
+    if (cls < 3) wl.qmax[cls] = std::max(wl.qmax[cls], (pg.g.W + 3) / 4);
+    else wl.has_long = true;
     for (uint32_t c = pg.c0; c < pg.c1; c += C) {
       const uint32_t c1 = std::min<uint32_t>(pg.c1, c + C);
       uint64_t colsum;
@@ -343,15 +364,15 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
       ci[cls].push_back(CostItem{(uint64_t)pg.g.W * colsum + 64, ItemDesc{gi, c, c1, 0}});
     }
   }
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 4; ++c) {
     std::stable_sort(ci[c].begin(), ci[c].end(), [](const CostItem& a, const CostItem& b) { return a.cost > b.cost; });
     r.begin[c] = (uint32_t)wl.items.size();
     for (const CostItem& x : ci[c]) wl.items.push_back(x.it);
     r.end[c] = (uint32_t)wl.items.size();
   }
-  r.begin[3] = (uint32_t)wl.prows.size();
+  r.begin[4] = (uint32_t)wl.prows.size();
   wl.prows.insert(wl.prows.end(), pr.begin(), pr.end());
-  r.end[3] = (uint32_t)wl.prows.size();
+  r.end[4] = (uint32_t)wl.prows.size();
   r.plain_pairs = plain_pairs;
   wl.max_plain_pairs = std::max(wl.max_plain_pairs, plain_pairs);
   wl.ranges.push_back(r);
@@ -371,22 +392,38 @@ int gpu_info(int device, GpuInfo* gi) {
 int StepExec::prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint32_t sig) {
   sigma = sig;
   for (int c = 0; c < 3; ++c) {
-    wmax[c] = wl.wmax[c];
+    qmax[c] = wl.qmax[c];
     waves[c] = lp.waves[c];
     blocks[c] = 0;
-    if (!wmax[c]) continue;
+    if (!qmax[c]) continue;
     int bpc = 0;
-    int e = fast_prepare(c, sigma, wmax[c], waves[c], &bpc);
+    int e = fast_prepare(c, sigma, qmax[c], waves[c], &bpc);
     if (e)
-      return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup (sigma %u, W %u, %u waves) failed: %s", c, sigma,
-                       wmax[c], waves[c], hipGetErrorString((hipError_t)e));
+      return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup (sigma %u, %u quads, %u waves) failed: %s", c, sigma,
+                       qmax[c], waves[c], hipGetErrorString((hipError_t)e));
     while (bpc == 0 && waves[c] > 1) {  // too many waves for the registers: shrink the workgroup
       waves[c] /= 2;
-      e = fast_prepare(c, sigma, wmax[c], waves[c], &bpc);
+      e = fast_prepare(c, sigma, qmax[c], waves[c], &bpc);
       if (e) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup failed", c);
     }
     if (bpc == 0) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d cannot be resident", c);
     blocks[c] = (uint32_t)(bpc * cus);
+  }
+  has_long = wl.has_long;
+  waves[3] = lp.waves[3];
+  blocks[3] = 0;
+  carry_words = 0;
+  if (has_long) {
+    int bpc = 0;
+    int e = long_prepare(sigma, waves[3], &bpc);
+    while (e == 0 && bpc == 0 && waves[3] > 1) {
+      waves[3] /= 2;
+      e = long_prepare(sigma, waves[3], &bpc);
+    }
+    if (e || bpc == 0)
+      return set_error(FAMSA_LCS_EDEVICE, "long-row kernel setup (sigma %u, %u waves) failed", sigma, waves[3]);
+    blocks[3] = (uint32_t)(bpc * cus);
+    carry_words = std::max<uint32_t>(1, (wl.long_col_max + 31) / 32);
   }
   w64max_plain = wl.prows.empty() ? 0 : std::max<uint32_t>(1, wl.w64max_plain);
   plain_blocks = wl.prows.empty() ? 0 : (uint32_t)(cus * 8);
@@ -394,21 +431,28 @@ int StepExec::prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint
 }
 
 int StepExec::enqueue(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint64_t* plain_work,
-                      hipStream_t s, hipEvent_t* ev) const {
+                      uint32_t* carry, hipStream_t s, hipEvent_t* ev) const {
   int e = launch_step_begin(ctl, s);
   if (e) return set_error(FAMSA_LCS_EDEVICE, "step_begin launch failed: %s", hipGetErrorString((hipError_t)e));
   for (int c = 0; c < 3; ++c) {
-    if (!wmax[c]) continue;
+    if (!qmax[c]) continue;
     if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c], s));
-    e = launch_fast(c, b, w, ctl, out, sigma, wmax[c], blocks[c], waves[c], s);
+    e = launch_fast(c, b, w, ctl, out, sigma, qmax[c], blocks[c], waves[c], s);
     if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_fast<%d> launch failed: %s", c, hipGetErrorString((hipError_t)e));
     if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c + 1], s));
   }
-  if (plain_blocks) {
+  if (has_long) {
+    if (!carry) return set_error(FAMSA_LCS_EDEVICE, "long-row kernel without a carry buffer");
     if (ev) FAMSA_HIP(hipEventRecord(ev[6], s));
+    e = launch_long(b, w, ctl, out, sigma, carry, carry_words, blocks[3], waves[3], s);
+    if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_long launch failed: %s", hipGetErrorString((hipError_t)e));
+    if (ev) FAMSA_HIP(hipEventRecord(ev[7], s));
+  }
+  if (plain_blocks) {
+    if (ev) FAMSA_HIP(hipEventRecord(ev[8], s));
     e = launch_plain(b, w, ctl, out, w64max_plain, plain_blocks, plain_work, s);
     if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_plain launch failed: %s", hipGetErrorString((hipError_t)e));
-    if (ev) FAMSA_HIP(hipEventRecord(ev[7], s));
+    if (ev) FAMSA_HIP(hipEventRecord(ev[9], s));
   }
   return 0;
 }

@@ -73,11 +73,12 @@ int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
 
 // A batch resident on the device with its masks.
 struct DeviceBatchOwner {
-  DevMem codes, dev_off, len, mask_off, masks, wprefix;
+  DevMem codes, dev_off, len, mask_off, masks, wprefix, sym, sym_off;
   std::vector<uint32_t> h_len;       // per sequence
   std::vector<uint64_t> h_lenprefix; // prefix sums of lengths (nseq + 1)
   std::vector<uint64_t> h_dev_off;   // device byte offset of each sequence in `codes`
   std::vector<uint64_t> h_mask_off;  // dword offset of each sequence's masks in `masks`
+  std::vector<uint64_t> h_sym_off;   // byte offset of each sequence's column stream in `sym`
   uint32_t nseq = 0, max_len = 0, sigma = 0;
   uint64_t bytes = 0;
   DeviceBatch view() const;
@@ -95,7 +96,7 @@ struct TileWork {
 };
 
 struct LaunchParams {
-  uint32_t waves[3] = {4, 8, 16};  // wavefronts per workgroup per class
+  uint32_t waves[4] = {4, 8, 16, 16};  // wavefronts per workgroup per class (3 = long rows)
   uint32_t cols_per_item = 256;
 };
 
@@ -108,9 +109,11 @@ struct WorkLists {
   std::vector<uint32_t> colmap;
   std::vector<uint64_t> rowbase;
   std::vector<StepRange> ranges;
-  uint32_t wmax[3] = {0, 0, 0};   // largest W per fast class
+  uint32_t qmax[3] = {0, 0, 0};   // largest mask quad count per fast class
+  bool has_long = false;           // items for the segmented long-row kernel
+  uint32_t long_col_max = 0;       // longest column a long-row item streams
   uint32_t w64max_plain = 0;       // largest ceil(len/64) in plain rows
-  uint64_t cells[4] = {0, 0, 0, 0};
+  uint64_t cells[5] = {0, 0, 0, 0, 0};
   uint64_t max_plain_pairs = 0;
 };
 
@@ -144,22 +147,26 @@ struct GpuInfo {
 };
 int gpu_info(int device, GpuInfo* gi);
 
-// Class of a group with W dwords per lane (3 = plain).
+// Class of a group with W dwords per lane (3 = segmented long rows).
 int class_of(uint32_t W, uint32_t sigma);
 
 // Executes the launches of one step for a set of descriptor arrays.
 struct StepExec {
   uint32_t sigma = 20;
-  uint32_t wmax[3] = {0, 0, 0};
-  uint32_t waves[3] = {4, 8, 16};
-  uint32_t blocks[3] = {0, 0, 0};
+  uint32_t qmax[3] = {0, 0, 0};
+  uint32_t waves[4] = {4, 8, 16, 16};
+  uint32_t blocks[4] = {0, 0, 0, 0};
+  bool has_long = false;
+  uint32_t carry_words = 0;        // per lane, for the longest column of a long-row item
   uint32_t plain_blocks = 0;
   uint32_t w64max_plain = 0;
   int prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint32_t sigma);
-  // Enqueue one step: step_begin + class kernels (those with work in the
-  // plan) + plain.  With `ev` != NULL records per-kernel events (ev[2*c], ev[2*c+1]).
+  uint64_t carry_bytes() const { return has_long ? (uint64_t)blocks[3] * waves[3] * carry_words * 64u * 4u : 0; }
+  // Enqueue one step: step_begin, then the kernels that have work in the plan
+  // (fast classes, long rows, plain).  With `ev` != NULL records per-kernel
+  // events ev[2c], ev[2c+1] for c = 0..4.
   int enqueue(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint64_t* plain_work,
-              hipStream_t s, hipEvent_t* ev) const;
+              uint32_t* carry, hipStream_t s, hipEvent_t* ev) const;
 };
 
 }  // namespace famsa

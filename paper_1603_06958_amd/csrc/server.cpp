@@ -57,7 +57,8 @@ struct Slot {
   DevMem d_out;
   PinMem h_out;
   DevMem d_groups, d_lanes, d_items, d_prows, d_colmap, d_rowbase, d_ranges, d_devoff, d_len, d_maskoff, d_ctl;
-  DevMem d_plainwork;
+  DevMem d_symoff;
+  DevMem d_plainwork, d_carry;
   StepExec exec;
   std::vector<StepTile> tiles;
   uint64_t values = 0;
@@ -94,7 +95,7 @@ struct famsa_lcs_server_s {
   // host staging kept alive until the step's uploads complete
   struct Staging {
     WorkLists wl;
-    std::vector<uint64_t> devoff, maskoff;
+    std::vector<uint64_t> devoff, maskoff, symoff;
     std::vector<uint32_t> len;
   } stage[2];
   ~famsa_lcs_server_s() {
@@ -139,6 +140,7 @@ int famsa_lcs_server_s::compose(Slot& sl, Staging& st) {
   std::vector<StepFamily> fams;
   st.devoff.clear();
   st.maskoff.clear();
+  st.symoff.clear();
   st.len.clear();
   std::vector<uint64_t> lenprefix(1, 0);
   for (Job* j : cand) {
@@ -159,8 +161,10 @@ int famsa_lcs_server_s::compose(Slot& sl, Staging& st) {
     sf.whole = j->whole;
     const DeviceBatchOwner& d = *j->dev;
     const uint64_t cbase = (uint64_t)(uintptr_t)d.codes.p, mbase = (uint64_t)(uintptr_t)d.masks.p / 4;
+    const uint64_t sbase = (uint64_t)(uintptr_t)d.sym.p;
     for (uint32_t i = 0; i < j->k; ++i) {
       st.devoff.push_back(cbase + d.h_dev_off[i]);
+      st.symoff.push_back(sbase + d.h_sym_off[i]);
       st.maskoff.push_back(mbase + d.h_mask_off[i]);
       st.len.push_back(d.h_len[i]);
       lenprefix.push_back(lenprefix.back() + d.h_len[i]);
@@ -192,7 +196,8 @@ int famsa_lcs_server_s::issue(int si) {
       (rc = upload_grow(sl.d_items, st.wl.items, s)) || (rc = upload_grow(sl.d_prows, st.wl.prows, s)) ||
       (rc = upload_grow(sl.d_colmap, st.wl.colmap, s)) || (rc = upload_grow(sl.d_rowbase, st.wl.rowbase, s)) ||
       (rc = upload_grow(sl.d_ranges, st.wl.ranges, s)) || (rc = upload_grow(sl.d_devoff, st.devoff, s)) ||
-      (rc = upload_grow(sl.d_len, st.len, s)) || (rc = upload_grow(sl.d_maskoff, st.maskoff, s)))
+      (rc = upload_grow(sl.d_len, st.len, s)) || (rc = upload_grow(sl.d_maskoff, st.maskoff, s)) ||
+      (rc = upload_grow(sl.d_symoff, st.symoff, s)))
     return rc;
   StepCtl hc{};
   hc.next_step = 0;
@@ -205,12 +210,15 @@ int famsa_lcs_server_s::issue(int si) {
     const uint64_t need = (uint64_t)sl.exec.plain_blocks * kPlainBlock * sl.exec.w64max_plain * 8;
     if (sl.d_plainwork.bytes < need && (rc = sl.d_plainwork.alloc(need))) return rc;
   }
-  DeviceBatch b{nullptr, sl.d_devoff.as<uint64_t>(), sl.d_len.as<uint32_t>(), sl.d_maskoff.as<uint64_t>(), nullptr};
+  DeviceBatch b{nullptr, sl.d_devoff.as<uint64_t>(),  nullptr, sl.d_symoff.as<uint64_t>(),
+                sl.d_len.as<uint32_t>(), sl.d_maskoff.as<uint64_t>(), nullptr};
   DeviceWork w{sl.d_groups.as<GroupDesc>(), sl.d_lanes.as<LaneDesc>(), sl.d_items.as<ItemDesc>(),
                sl.d_prows.as<PlainRow>(), sl.d_colmap.as<uint32_t>(), sl.d_rowbase.as<uint64_t>(),
                sl.d_ranges.as<StepRange>()};
-  if ((rc = sl.exec.enqueue(b, w, sl.d_ctl.as<StepCtl>(), sl.d_out.as<int32_t>(), sl.d_plainwork.as<uint64_t>(), s,
-                            nullptr)))
+  if (sl.exec.has_long && sl.d_carry.bytes < sl.exec.carry_bytes() && (rc = sl.d_carry.alloc(sl.exec.carry_bytes())))
+    return rc;
+  if ((rc = sl.exec.enqueue(b, w, sl.d_ctl.as<StepCtl>(), sl.d_out.as<int32_t>(), sl.d_plainwork.as<uint64_t>(),
+                            sl.d_carry.as<uint32_t>(), s, nullptr)))
     return rc;
   FAMSA_HIP(hipEventRecord(sl.done, s));
   FAMSA_HIP(hipStreamWaitEvent(xs, sl.done, 0));

@@ -14,7 +14,7 @@ DT = {
     "tiles": np.dtype([("fam", "<u4"), ("r0", "<u4"), ("r1", "<u4"), ("step", "<u4"), ("count", "<u8"),
                        ("out_off", "<u8")]),
     "steps": np.dtype([("tile_begin", "<u8"), ("tile_end", "<u8"), ("values", "<u8")]),
-    "ranges": np.dtype([("begin", "<u4", 4), ("end", "<u4", 4), ("plain_pairs", "<u8")]),
+    "ranges": np.dtype([("begin", "<u4", 5), ("end", "<u4", 5), ("plain_pairs", "<u8")]),
     "groups": np.dtype([("lane_first", "<u4"), ("nrows", "<u4"), ("W", "<u4"), ("fam_base", "<u4"),
                         ("colmap_base", "<u4"), ("rowbase_base", "<u4"), ("pad0", "<u4"), ("pad1", "<u4")]),
     "lanes": np.dtype([("out_off", "<u8"), ("seq", "<u4"), ("pos", "<u4"), ("orig", "<u4"), ("pad", "<u4")]),
@@ -65,7 +65,7 @@ def emulate_step(d, s):
     r = d["ranges"][s]
     offs, gi, gj = [], [], []
     colmap, rowbase = d["colmap"], d["rowbase"]
-    for cls in range(3):
+    for cls in range(4):  # fast classes and the segmented long-row kernel share the item layout
         for it in d["items"][r["begin"][cls]:r["end"][cls]]:
             g = d["groups"][it["group"]]
             ln = d["lanes"][g["lane_first"]:g["lane_first"] + g["nrows"]]
@@ -84,7 +84,7 @@ def emulate_step(d, s):
                 offs.append(o)
                 gi.append(np.full(bb.size, int(g["fam_base"]) + orig))
                 gj.append(int(g["fam_base"]) + bb)
-    rows = d["prows"][r["begin"][3]:r["end"][3]]
+    rows = d["prows"][r["begin"][4]:r["end"][4]]
     total = int(r["plain_pairs"])
     if total:
         p = np.arange(total, dtype=np.int64)
