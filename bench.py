@@ -89,7 +89,7 @@ def cpu_baseline(b, seconds_target=12.0, seed=7):
 def run_main(b, steps, warmup, tile_rows=1024, tune=True):
     from paper_1603_06958_amd import binding as B
     import torch
-    p = B.Plan.from_batch(b, tile_rows=tile_rows, flags=B.NO_GRAPH)
+    p = B.Plan.from_batch(b, tile_rows=tile_rows)
     if tune:
         t0 = time.perf_counter()
         p.autotune(os.environ.get("FAMSA_LCS_TUNE_CACHE") or None)
@@ -160,7 +160,18 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (for scaling HBM byte counters)")
     a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the stage on a single MI355X "
               "(the multi-GPU sharding is a design, not a run); use --gpus 1", file=sys.stderr)
@@ -195,6 +206,7 @@ def main():
                    "k": b.nseq, "pairs": info.pairs, "cells": cells, "tile_rows": 1024,
                    "delivery": "host pinned memory, callback per tile"},
         "pairs_per_s": round(info.pairs / (ms / 1e3), 1),
+        "whole_job_alu_frac": round(cells * OPS_PER_CELL / (ms / 1e3) / PEAK_INT_OPS, 4),
         "device_gcups": round(cells / (kst[-1].step_ms / 1e3) / 1e9, 1),
         "peak_hbm_bytes": int(info.device_bytes),
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_INT_OPS / 1e12, 3),

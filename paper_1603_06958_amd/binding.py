@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfamsa_lcs.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5
-PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE = 0x1, 0x2, 0x4, 0x8, 0x10
+PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE, ONE_STREAM = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 MAX_LEN = 65535
 
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECANCELED: "ECANCELED", EBUSY: "EBUSY"}

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <map>
 
 #include "runtime.h"
 
@@ -47,10 +48,12 @@ struct famsa_lcs_plan_s {
   PinMem h_out[2];
   uint64_t step_cap = 0;  // values per step buffer
   hipStream_t cs[2] = {nullptr, nullptr};
-  hipStream_t xs = nullptr;
+  static constexpr int kCopyStreams = 4;  // device-to-host copies split across DMA engines
+  hipStream_t xs[kCopyStreams] = {};
+  hipEvent_t ev_xdone[2][kCopyStreams] = {};
   hipEvent_t ev_comp[2] = {}, ev_copy[2] = {}, ev_s0[2] = {}, ev_s1[2] = {}, ev_user = nullptr;
   hipEvent_t ev_k[2][10] = {};
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::map<uint64_t, hipGraphExec_t> graphs[2];  // per compute stream, per launch signature
   std::atomic<int> busy{0};
   famsa_lcs_stats stats{};
   uint64_t pairs = 0, cells = 0;
@@ -62,7 +65,15 @@ struct famsa_lcs_plan_s {
   }
   StepCtl* ctl(int slot) const { return d_ctl.as<StepCtl>() + slot; }
   bool plain() const { return opt.flags & FAMSA_LCS_PLAIN; }
-  bool use_graph() const { return !(opt.flags & (FAMSA_LCS_NO_GRAPH | FAMSA_LCS_PLAIN)); }
+  // compute stream of a buffer slot: both slots share stream 0 under ONE_STREAM
+  hipStream_t cstream(int slot) const { return (opt.flags & FAMSA_LCS_ONE_STREAM) ? cs[0] : cs[slot]; }
+  // Graph replays of two streams do not overlap on this runtime, while direct
+  // launches do; so graphs are used where there is nothing to overlap: plans
+  // of one launch step (the batched form), or one compute stream.
+  bool use_graph() const {
+    if (opt.flags & (FAMSA_LCS_NO_GRAPH | FAMSA_LCS_PLAIN)) return false;
+    return steps.size() <= 1 || (opt.flags & FAMSA_LCS_ONE_STREAM);
+  }
   ~famsa_lcs_plan_s();
   int build_tiles_and_steps();
   int build_work();
@@ -72,6 +83,12 @@ struct famsa_lcs_plan_s {
   int capture_graphs();
   int enqueue_step(uint64_t s, int slot, bool timed);
   int upload_work();
+  void drop_graphs() {
+    for (auto& m : graphs) {
+      for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
+      m.clear();
+    }
+  }
   int autotune(const char* path);
   int run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user);
 };
@@ -80,9 +97,10 @@ famsa_lcs_plan_s::~famsa_lcs_plan_s() {
   for (int i = 0; i < 2; ++i) {
     if (cs[i]) (void)hipStreamSynchronize(cs[i]);
   }
-  if (xs) (void)hipStreamSynchronize(xs);
+  for (hipStream_t x : xs)
+    if (x) (void)hipStreamSynchronize(x);
+  drop_graphs();
   for (int i = 0; i < 2; ++i) {
-    if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
     if (ev_comp[i]) (void)hipEventDestroy(ev_comp[i]);
     if (ev_copy[i]) (void)hipEventDestroy(ev_copy[i]);
     if (ev_s0[i]) (void)hipEventDestroy(ev_s0[i]);
@@ -92,7 +110,11 @@ famsa_lcs_plan_s::~famsa_lcs_plan_s() {
     if (cs[i]) (void)hipStreamDestroy(cs[i]);
   }
   if (ev_user) (void)hipEventDestroy(ev_user);
-  if (xs) (void)hipStreamDestroy(xs);
+  for (int i = 0; i < 2; ++i)
+    for (hipEvent_t e : ev_xdone[i])
+      if (e) (void)hipEventDestroy(e);
+  for (hipStream_t x : xs)
+    if (x) (void)hipStreamDestroy(x);
 }
 
 int famsa_lcs_plan_s::build_tiles_and_steps() {
@@ -194,7 +216,9 @@ int famsa_lcs_plan_s::dump(const char* path) const {
 int famsa_lcs_plan_s::setup_device() {
   FAMSA_HIP(hipStreamCreateWithFlags(&cs[0], hipStreamNonBlocking));
   FAMSA_HIP(hipStreamCreateWithFlags(&cs[1], hipStreamNonBlocking));
-  FAMSA_HIP(hipStreamCreateWithFlags(&xs, hipStreamNonBlocking));
+  for (hipStream_t& x : xs) FAMSA_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+  for (int i = 0; i < 2; ++i)
+    for (hipEvent_t& e : ev_xdone[i]) FAMSA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (int i = 0; i < 2; ++i) {
     FAMSA_HIP(hipEventCreateWithFlags(&ev_comp[i], hipEventDisableTiming));
     FAMSA_HIP(hipEventCreateWithFlags(&ev_copy[i], hipEventDisableTiming));
@@ -206,36 +230,46 @@ int famsa_lcs_plan_s::setup_device() {
   return 0;
 }
 
+// One graph per compute stream and distinct launch signature of the plan's
+// steps; a replay advances that stream's step counter and runs the step.
 int famsa_lcs_plan_s::capture_graphs() {
   const DeviceBatch b = batch.view();
   const DeviceWork w = work();
   for (int slot = 0; slot < 2; ++slot) {
-    hipGraph_t g = nullptr;
-    FAMSA_HIP(hipStreamBeginCapture(cs[slot], hipStreamCaptureModeThreadLocal));
-    int rc = exec.enqueue(b, w, ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(),
-                          d_carry[slot].as<uint32_t>(), cs[slot], nullptr);
-    hipError_t e = hipStreamEndCapture(cs[slot], &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
+    for (const StepSig& sg : wl.sigs) {
+      if (graphs[slot].count(sg.key())) continue;
+      hipGraph_t g = nullptr;
+      FAMSA_HIP(hipStreamBeginCapture(cs[slot], hipStreamCaptureModeThreadLocal));
+      int rc = exec.enqueue(sg, b, w, ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(),
+                            d_carry[slot].as<uint32_t>(), cs[slot], nullptr);
+      hipError_t e = hipStreamEndCapture(cs[slot], &g);  // a graph can be launched on any stream
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return set_error(FAMSA_LCS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return set_error(FAMSA_LCS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      graphs[slot][sg.key()] = x;
     }
-    if (e != hipSuccess) return set_error(FAMSA_LCS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&graph[slot], g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return set_error(FAMSA_LCS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
   return 0;
 }
 
 int famsa_lcs_plan_s::enqueue_step(uint64_t s, int slot, bool timed) {
-  (void)s;
-  hipStream_t st = cs[slot];
+  hipStream_t st = cstream(slot);
   FAMSA_HIP(hipEventRecord(ev_s0[slot], st));
+  const StepSig& sg = wl.sigs[s];
   if (use_graph()) {
-    FAMSA_HIP(hipGraphLaunch(graph[slot], st));
+    auto it = graphs[slot].find(sg.key());
+    if (it == graphs[slot].end()) return set_error(FAMSA_LCS_EDEVICE, "no graph for step %llu", (unsigned long long)s);
+    FAMSA_HIP(hipGraphLaunch(it->second, st));
   } else {
-    int rc = exec.enqueue(batch.view(), work(), ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(),
-                          d_carry[slot].as<uint32_t>(), st, timed ? ev_k[slot] : nullptr);
+    int rc = exec.enqueue(sg, batch.view(), work(), ctl(slot), d_out[slot].as<int32_t>(),
+                          d_plainwork[slot].as<uint64_t>(), d_carry[slot].as<uint32_t>(), st,
+                          timed ? ev_k[slot] : nullptr);
     if (rc) return rc;
   }
   FAMSA_HIP(hipEventRecord(ev_s1[slot], st));
@@ -332,11 +366,7 @@ int famsa_lcs_plan_s::autotune(const char* path) {
   int rc;
   if ((rc = tune_store(gi, opt.sigma, lp, path))) return rc;
   // rebuild the work lists, launch shapes and graphs with the winner
-  for (int i = 0; i < 2; ++i)
-    if (graph[i]) {
-      (void)hipGraphExecDestroy(graph[i]);
-      graph[i] = nullptr;
-    }
+  drop_graphs();
   wl = WorkLists();
   if ((rc = build_work())) return rc;
   if ((rc = upload_work())) return rc;
@@ -380,22 +410,35 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
   const auto t0 = std::chrono::steady_clock::now();
   auto issue = [&](uint64_t s) -> int {
     const int slot = (int)(s % nslots);
-    if (s >= s0 + nslots) FAMSA_HIP(hipStreamWaitEvent(cs[slot], ev_copy[slot], 0));  // buffer reuse
+    if (s >= s0 + nslots) FAMSA_HIP(hipStreamWaitEvent(cstream(slot), ev_copy[slot], 0));  // buffer reuse
     int rc = enqueue_step(s, slot, timed);
     if (rc) return rc;
     if (!dev_tiles) {
-      FAMSA_HIP(hipStreamWaitEvent(xs, ev_comp[slot], 0));
-      FAMSA_HIP(hipMemcpyAsync(h_out[slot].p, d_out[slot].p, steps[s].values * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, xs));
-      FAMSA_HIP(hipEventRecord(ev_copy[slot], xs));
+      // split the step's values over the copy streams; the last one joins them
+      const uint64_t bytes = steps[s].values * sizeof(int32_t);
+      const uint64_t part = (bytes / kCopyStreams + 4095) & ~4095ull;
+      int used = 0;
+      for (int x = 0; x < kCopyStreams; ++x) {
+        const uint64_t off = part * x;
+        if (off >= bytes) break;
+        const uint64_t n = std::min(part, bytes - off);
+        FAMSA_HIP(hipStreamWaitEvent(xs[x], ev_comp[slot], 0));
+        FAMSA_HIP(hipMemcpyAsync(static_cast<char*>(h_out[slot].p) + off, static_cast<char*>(d_out[slot].p) + off, n,
+                                 hipMemcpyDeviceToHost, xs[x]));
+        FAMSA_HIP(hipEventRecord(ev_xdone[slot][x], xs[x]));
+        ++used;
+      }
+      if (used == 0) FAMSA_HIP(hipStreamWaitEvent(xs[0], ev_comp[slot], 0));
+      for (int x = 1; x < used; ++x) FAMSA_HIP(hipStreamWaitEvent(xs[0], ev_xdone[slot][x], 0));
+      FAMSA_HIP(hipEventRecord(ev_copy[slot], xs[0]));
     } else {
-      FAMSA_HIP(hipEventRecord(ev_copy[slot], cs[slot]));
+      FAMSA_HIP(hipEventRecord(ev_copy[slot], cstream(slot)));
     }
     return 0;
   };
   auto drain = [&]() {
     for (int i = 0; i < 2; ++i) (void)hipStreamSynchronize(cs[i]);
-    (void)hipStreamSynchronize(xs);
+    for (hipStream_t x : xs) (void)hipStreamSynchronize(x);
   };
   int rc = 0;
   for (uint64_t s = s0; s < ns && s < s0 + nslots && !rc; ++s) rc = issue(s);
@@ -412,7 +455,7 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
     if (timed) {
       for (int c = 0; c < 5; ++c) {
         float km = 0.f;
-        if ((c < 3 ? exec.qmax[c] != 0 : c == 3 ? exec.has_long : exec.plain_blocks != 0) &&
+        if (wl.sigs[s].has(c) &&
             hipEventElapsedTime(&km, ev_k[slot][2 * c], ev_k[slot][2 * c + 1]) == hipSuccess) {
           stats.kernel_ms[c] += km;
           stats.launches[c] += 1;
@@ -429,7 +472,7 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
       tile.row_end = tl.r1;
       tile.count = tl.count;
       tile.lcs = (dev_tiles ? d_out[slot].as<int32_t>() : h_out[slot].as<int32_t>()) + tl.out_off;
-      tile.stream = cs[slot];
+      tile.stream = cstream(slot);
       if (fn(user, &tile) != 0) {
         rc = set_error(FAMSA_LCS_ECANCELED, "tile callback returned nonzero at tile %llu", (unsigned long long)t);
         break;

@@ -81,7 +81,7 @@ int normalize_options(const famsa_lcs_options* in, Opts* o) {
   if (d.tile_rows < 1) return set_error(FAMSA_LCS_EINVAL, "tile_rows must be >= 1");
   if (d.device < 0) return set_error(FAMSA_LCS_EINVAL, "device %d < 0", d.device);
   const uint32_t known = FAMSA_LCS_PLAIN | FAMSA_LCS_DESCENDING | FAMSA_LCS_DEVICE_TILES | FAMSA_LCS_NO_GRAPH |
-                         FAMSA_LCS_NO_AUTOTUNE;
+                         FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM;
   if (d.flags & ~known) return set_error(FAMSA_LCS_EINVAL, "unknown flag bits 0x%x", d.flags & ~known);
   if (d.cols_per_item > (1u << 20)) return set_error(FAMSA_LCS_EINVAL, "cols_per_item %u too large", d.cols_per_item);
   o->sigma = d.alphabet_size;
@@ -304,42 +304,49 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
         span += k - (P + 1);
       }
     } else {
-      for (const TileWork& t : sf.tiles) {
-        std::vector<uint32_t> rows(t.r1 - t.r0);
-        std::iota(rows.begin(), rows.end(), t.r0);
-        if (!plain_only)
-          std::stable_sort(rows.begin(), rows.end(),
-                           [&](uint32_t a, uint32_t b) { return len[fb + a] > len[fb + b]; });
-        for (size_t P = 0; P < rows.size(); P += kLanes) {
-          const uint32_t nrows = (uint32_t)std::min<size_t>(kLanes, rows.size() - P);
-          uint32_t maxlen = 0, mini = 0xFFFFFFFFu;
-          for (uint32_t l = 0; l < nrows; ++l) {
-            maxlen = std::max(maxlen, len[fb + rows[P + l]]);
-            mini = std::min(mini, rows[P + l]);
-          }
-          if (mini + 1 >= k) continue;  // only the last row: no pairs
-          const uint32_t W = std::max<uint32_t>(1, (maxlen + 31) / 32);
-          GroupDesc g{};
-          g.lane_first = (uint32_t)wl.lanes.size();
-          g.nrows = nrows;
-          g.W = W;
-          g.fam_base = fb;
-          g.colmap_base = kNoMap;
-          g.rowbase_base = kNoMap;
-          const int cls = plain_only ? 4 : class_of(W, sigma);
-          for (uint32_t l = 0; l < nrows; ++l) {
-            const uint32_t i = rows[P + l];
-            LaneDesc ld{t.out_off + tri_rows(k, t.r0, i), fb + i, i, i, 0};
-            wl.cells[cls] += (uint64_t)len[fb + i] * (lenprefix[fb + k] - lenprefix[fb + i + 1]);
-            if (cls < 4) wl.lanes.push_back(ld);
-            else add_plain(ld, fb, k, kNoMap, kNoMap);
-          }
-          if (cls == 3)
-            for (uint32_t j = mini + 1; j < k; ++j) wl.long_col_max = std::max(wl.long_col_max, len[fb + j]);
-          if (cls < 4) {
-            pend.push_back(PendingGroup{g, mini + 1, k, nullptr, lenprefix[fb]});
-            span += k - (mini + 1);
-          }
+      // tile mode: the rows of all this family's tiles in the step, pooled
+      // and sorted by length so each group's rows have similar lengths
+      std::vector<uint32_t> rows;
+      std::vector<uint64_t> rowoff;  // step offset of (i, i+1), by position in `rows`
+      for (const TileWork& t : sf.tiles)
+        for (uint32_t i = t.r0; i < t.r1; ++i) {
+          rows.push_back(i);
+          rowoff.push_back(t.out_off + tri_rows(k, t.r0, i));
+        }
+      std::vector<uint32_t> ord(rows.size());
+      std::iota(ord.begin(), ord.end(), 0u);
+      if (!plain_only)
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](uint32_t a, uint32_t b) { return len[fb + rows[a]] > len[fb + rows[b]]; });
+      for (size_t P = 0; P < ord.size(); P += kLanes) {
+        const uint32_t nrows = (uint32_t)std::min<size_t>(kLanes, ord.size() - P);
+        uint32_t maxlen = 0, mini = 0xFFFFFFFFu;
+        for (uint32_t l = 0; l < nrows; ++l) {
+          maxlen = std::max(maxlen, len[fb + rows[ord[P + l]]]);
+          mini = std::min(mini, rows[ord[P + l]]);
+        }
+        if (mini + 1 >= k) continue;  // only the last row: no pairs
+        const uint32_t W = std::max<uint32_t>(1, (maxlen + 31) / 32);
+        GroupDesc g{};
+        g.lane_first = (uint32_t)wl.lanes.size();
+        g.nrows = nrows;
+        g.W = W;
+        g.fam_base = fb;
+        g.colmap_base = kNoMap;
+        g.rowbase_base = kNoMap;
+        const int cls = plain_only ? 4 : class_of(W, sigma);
+        for (uint32_t l = 0; l < nrows; ++l) {
+          const uint32_t i = rows[ord[P + l]];
+          LaneDesc ld{rowoff[ord[P + l]], fb + i, i, i, 0};
+          wl.cells[cls] += (uint64_t)len[fb + i] * (lenprefix[fb + k] - lenprefix[fb + i + 1]);
+          if (cls < 4) wl.lanes.push_back(ld);
+          else add_plain(ld, fb, k, kNoMap, kNoMap);
+        }
+        if (cls == 3)
+          for (uint32_t j = mini + 1; j < k; ++j) wl.long_col_max = std::max(wl.long_col_max, len[fb + j]);
+        if (cls < 4) {
+          pend.push_back(PendingGroup{g, mini + 1, k, nullptr, lenprefix[fb]});
+          span += k - (mini + 1);
         }
       }
     }
@@ -350,12 +357,19 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
   uint32_t C = lp.cols_per_item ? lp.cols_per_item : 256;
   const uint64_t want_items = 4096;
   if (span / C < want_items) C = (uint32_t)std::max<uint64_t>(16, std::min<uint64_t>(C, span / want_items));
+  StepSig sig;
   for (const PendingGroup& pg : pend) {
     const uint32_t gi = (uint32_t)wl.groups.size();
     wl.groups.push_back(pg.g);
     const int cls = class_of(pg.g.W, sigma);
-    if (cls < 3) wl.qmax[cls] = std::max(wl.qmax[cls], (pg.g.W + 3) / 4);
-    else wl.has_long = true;
+    const uint32_t q = (pg.g.W + 3) / 4;
+    if (cls < 3) {
+      wl.qmax[cls] = std::max(wl.qmax[cls], q);
+      sig.q[cls] = (uint8_t)std::max<uint32_t>(sig.q[cls], q);
+    } else {
+      wl.has_long = true;
+      sig.lng = 1;
+    }
     for (uint32_t c = pg.c0; c < pg.c1; c += C) {
       const uint32_t c1 = std::min<uint32_t>(pg.c1, c + C);
       uint64_t colsum;
@@ -375,7 +389,9 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
   r.end[4] = (uint32_t)wl.prows.size();
   r.plain_pairs = plain_pairs;
   wl.max_plain_pairs = std::max(wl.max_plain_pairs, plain_pairs);
+  sig.plain = plain_pairs ? 1 : 0;
   wl.ranges.push_back(r);
+  wl.sigs.push_back(sig);
 }
 
 int gpu_info(int device, GpuInfo* gi) {
@@ -389,40 +405,46 @@ int gpu_info(int device, GpuInfo* gi) {
   return 0;
 }
 
-int StepExec::prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint32_t sig) {
+int StepExec::prepare(int ncu, const LaunchParams& lp, const WorkLists& wl, uint32_t sig) {
   sigma = sig;
+  cus = ncu;
   for (int c = 0; c < 3; ++c) {
     qmax[c] = wl.qmax[c];
     waves[c] = lp.waves[c];
-    blocks[c] = 0;
+    for (int q = 0; q < 8; ++q) bpc[c][q] = 0;
     if (!qmax[c]) continue;
-    int bpc = 0;
-    int e = fast_prepare(c, sigma, qmax[c], waves[c], &bpc);
-    if (e)
-      return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup (sigma %u, %u quads, %u waves) failed: %s", c, sigma,
-                       qmax[c], waves[c], hipGetErrorString((hipError_t)e));
-    while (bpc == 0 && waves[c] > 1) {  // too many waves for the registers: shrink the workgroup
-      waves[c] /= 2;
-      e = fast_prepare(c, sigma, qmax[c], waves[c], &bpc);
-      if (e) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup failed", c);
+    // every quad count a step of this class may use
+    bool need[8] = {};
+    for (const StepSig& s : wl.sigs)
+      if (s.q[c]) need[s.q[c]] = true;
+    for (int q = 1; q < 8; ++q) {
+      if (!need[q]) continue;
+      int n = 0;
+      int e = fast_prepare(c, sigma, (uint32_t)q, waves[c], &n);
+      while (e == 0 && n == 0 && waves[c] > 1) {  // too many waves for the registers: shrink the workgroup
+        waves[c] /= 2;
+        e = fast_prepare(c, sigma, (uint32_t)q, waves[c], &n);
+      }
+      if (e || n == 0)
+        return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d setup (sigma %u, %d quads, %u waves) failed: %s", c, sigma,
+                         q, waves[c], e ? hipGetErrorString((hipError_t)e) : "not resident");
+      bpc[c][q] = (uint32_t)n;
     }
-    if (bpc == 0) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d cannot be resident", c);
-    blocks[c] = (uint32_t)(bpc * cus);
   }
   has_long = wl.has_long;
   waves[3] = lp.waves[3];
   blocks[3] = 0;
   carry_words = 0;
   if (has_long) {
-    int bpc = 0;
-    int e = long_prepare(sigma, waves[3], &bpc);
-    while (e == 0 && bpc == 0 && waves[3] > 1) {
+    int n = 0;
+    int e = long_prepare(sigma, waves[3], &n);
+    while (e == 0 && n == 0 && waves[3] > 1) {
       waves[3] /= 2;
-      e = long_prepare(sigma, waves[3], &bpc);
+      e = long_prepare(sigma, waves[3], &n);
     }
-    if (e || bpc == 0)
+    if (e || n == 0)
       return set_error(FAMSA_LCS_EDEVICE, "long-row kernel setup (sigma %u, %u waves) failed", sigma, waves[3]);
-    blocks[3] = (uint32_t)(bpc * cus);
+    blocks[3] = (uint32_t)(n * cus);
     carry_words = std::max<uint32_t>(1, (wl.long_col_max + 31) / 32);
   }
   w64max_plain = wl.prows.empty() ? 0 : std::max<uint32_t>(1, wl.w64max_plain);
@@ -430,25 +452,27 @@ int StepExec::prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint
   return 0;
 }
 
-int StepExec::enqueue(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint64_t* plain_work,
-                      uint32_t* carry, hipStream_t s, hipEvent_t* ev) const {
+int StepExec::enqueue(const StepSig& sig, const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out,
+                      uint64_t* plain_work, uint32_t* carry, hipStream_t s, hipEvent_t* ev) const {
   int e = launch_step_begin(ctl, s);
   if (e) return set_error(FAMSA_LCS_EDEVICE, "step_begin launch failed: %s", hipGetErrorString((hipError_t)e));
-  for (int c = 0; c < 3; ++c) {
-    if (!qmax[c]) continue;
-    if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c], s));
-    e = launch_fast(c, b, w, ctl, out, sigma, qmax[c], blocks[c], waves[c], s);
-    if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_fast<%d> launch failed: %s", c, hipGetErrorString((hipError_t)e));
-    if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c + 1], s));
-  }
-  if (has_long) {
+  if (sig.lng) {
     if (!carry) return set_error(FAMSA_LCS_EDEVICE, "long-row kernel without a carry buffer");
     if (ev) FAMSA_HIP(hipEventRecord(ev[6], s));
     e = launch_long(b, w, ctl, out, sigma, carry, carry_words, blocks[3], waves[3], s);
     if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_long launch failed: %s", hipGetErrorString((hipError_t)e));
     if (ev) FAMSA_HIP(hipEventRecord(ev[7], s));
   }
-  if (plain_blocks) {
+  for (int c = 2; c >= 0; --c) {
+    const uint32_t q = sig.q[c];
+    if (!q) continue;
+    if (q >= 8 || !bpc[c][q]) return set_error(FAMSA_LCS_EDEVICE, "fast kernel %d was not prepared for %u quads", c, q);
+    if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c], s));
+    e = launch_fast(c, b, w, ctl, out, sigma, q, bpc[c][q] * (uint32_t)cus, waves[c], s);
+    if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_fast<%d> launch failed: %s", c, hipGetErrorString((hipError_t)e));
+    if (ev) FAMSA_HIP(hipEventRecord(ev[2 * c + 1], s));
+  }
+  if (sig.plain) {
     if (ev) FAMSA_HIP(hipEventRecord(ev[8], s));
     e = launch_plain(b, w, ctl, out, w64max_plain, plain_blocks, plain_work, s);
     if (e) return set_error(FAMSA_LCS_EDEVICE, "lcs_plain launch failed: %s", hipGetErrorString((hipError_t)e));

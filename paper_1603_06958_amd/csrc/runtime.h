@@ -100,6 +100,20 @@ struct LaunchParams {
   uint32_t cols_per_item = 256;
 };
 
+// The launches one step needs: for each fast class the quad count of its
+// widest group (0: no items), and whether long-row items and plain rows
+// exist.  LDS and grid sizes follow it, so a step never launches a kernel
+// that has nothing to do or reserves more LDS than it uses.
+struct StepSig {
+  uint8_t q[3] = {0, 0, 0};
+  uint8_t lng = 0, plain = 0;
+  uint64_t key() const {
+    return (uint64_t)q[0] | ((uint64_t)q[1] << 8) | ((uint64_t)q[2] << 16) | ((uint64_t)lng << 24) |
+           ((uint64_t)plain << 32);
+  }
+  bool has(int c) const { return c < 3 ? q[c] != 0 : (c == 3 ? lng != 0 : plain != 0); }
+};
+
 // Host copies of the descriptor arrays for one or more steps.
 struct WorkLists {
   std::vector<GroupDesc> groups;
@@ -109,6 +123,7 @@ struct WorkLists {
   std::vector<uint32_t> colmap;
   std::vector<uint64_t> rowbase;
   std::vector<StepRange> ranges;
+  std::vector<StepSig> sigs;       // per step
   uint32_t qmax[3] = {0, 0, 0};   // largest mask quad count per fast class
   bool has_long = false;           // items for the segmented long-row kernel
   uint32_t long_col_max = 0;       // longest column a long-row item streams
@@ -153,20 +168,22 @@ int class_of(uint32_t W, uint32_t sigma);
 // Executes the launches of one step for a set of descriptor arrays.
 struct StepExec {
   uint32_t sigma = 20;
-  uint32_t qmax[3] = {0, 0, 0};
+  uint32_t qmax[3] = {0, 0, 0};        // plan-wide, per fast class
   uint32_t waves[4] = {4, 8, 16, 16};
-  uint32_t blocks[4] = {0, 0, 0, 0};
+  uint32_t bpc[3][8] = {};             // resident workgroups per CU for fast class c at q quads
+  uint32_t blocks[4] = {0, 0, 0, 0};   // [3]: long-row kernel grid
+  int cus = 256;
   bool has_long = false;
-  uint32_t carry_words = 0;        // per lane, for the longest column of a long-row item
+  uint32_t carry_words = 0;            // per lane, for the longest column of a long-row item
   uint32_t plain_blocks = 0;
   uint32_t w64max_plain = 0;
   int prepare(int cus, const LaunchParams& lp, const WorkLists& wl, uint32_t sigma);
   uint64_t carry_bytes() const { return has_long ? (uint64_t)blocks[3] * waves[3] * carry_words * 64u * 4u : 0; }
-  // Enqueue one step: step_begin, then the kernels that have work in the plan
-  // (fast classes, long rows, plain).  With `ev` != NULL records per-kernel
-  // events ev[2c], ev[2c+1] for c = 0..4.
-  int enqueue(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint64_t* plain_work,
-              uint32_t* carry, hipStream_t s, hipEvent_t* ev) const;
+  // Enqueue one step: step_begin, then the step's kernels heaviest first
+  // (long rows, fast classes 2, 1, 0, plain).  With `ev` != NULL records
+  // per-kernel events ev[2c], ev[2c+1] for c = 0..4.
+  int enqueue(const StepSig& sig, const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out,
+              uint64_t* plain_work, uint32_t* carry, hipStream_t s, hipEvent_t* ev) const;
 };
 
 }  // namespace famsa

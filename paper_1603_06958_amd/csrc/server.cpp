@@ -217,8 +217,8 @@ int famsa_lcs_server_s::issue(int si) {
                sl.d_ranges.as<StepRange>()};
   if (sl.exec.has_long && sl.d_carry.bytes < sl.exec.carry_bytes() && (rc = sl.d_carry.alloc(sl.exec.carry_bytes())))
     return rc;
-  if ((rc = sl.exec.enqueue(b, w, sl.d_ctl.as<StepCtl>(), sl.d_out.as<int32_t>(), sl.d_plainwork.as<uint64_t>(),
-                            sl.d_carry.as<uint32_t>(), s, nullptr)))
+  if ((rc = sl.exec.enqueue(st.wl.sigs[0], b, w, sl.d_ctl.as<StepCtl>(), sl.d_out.as<int32_t>(),
+                            sl.d_plainwork.as<uint64_t>(), sl.d_carry.as<uint32_t>(), s, nullptr)))
     return rc;
   FAMSA_HIP(hipEventRecord(sl.done, s));
   FAMSA_HIP(hipStreamWaitEvent(xs, sl.done, 0));

@@ -18,8 +18,9 @@ from . import binding as B
 from . import inputs
 
 # Arrival rate for the c5 serving workload, in jobs per second: 0.7 x the
-# saturated job throughput measured on one MI355X (c5 job mix, full k range).
-C5_RATE_PER_S = 12.0
+# saturated job throughput measured on one MI355X (c5 job mix, full k range:
+# 40 jobs in 0.84 s, 47.6 jobs/s).
+C5_RATE_PER_S = 33.3
 
 
 class Server:
