@@ -204,6 +204,31 @@ uint32_t famsa_slink_rows_done(const famsa_slink_t* s);
 void famsa_slink_destroy(famsa_slink_t* s);
 
 /* ------------------------------------------------------------------------
+ * Single linkage on the GPU.  Single linkage merges clusters in the order of
+ * the maximum spanning tree of the similarities, so instead of SLINK's
+ * pointer representation this consumer keeps that tree on the device: after
+ * each device tile (FAMSA_LCS_DEVICE_TILES) it replaces its forest with the
+ * maximum spanning forest of the forest plus the tile's pairs (Boruvka
+ * rounds on the GPU).  Memory is O(k) on the device; tiles may come in any
+ * order.  Similarities are ordered exactly; equal similarities are ordered
+ * by the pair (u, v), u < v, so the tree is unique.
+ * ------------------------------------------------------------------------ */
+typedef struct famsa_mst_s famsa_mst_t;
+
+/* lengths: the k sequence lengths of the family (copied to `device`). */
+int famsa_mst_create(const uint32_t* lengths, uint32_t k, int device, famsa_mst_t** out);
+/* A famsa_lcs_tile_fn for device tiles: pass the famsa_mst_t* as `user`.
+ * Orders its GPU work on tile->stream and returns when the tile is merged
+ * (nonzero on a bad tile or a HIP error). */
+int famsa_mst_consume(void* mst, const famsa_lcs_tile* tile);
+/* The forest's edges (k-1 of them once every pair has been seen): endpoints
+ * u < v (family-local), their LCS and indel^2 (similarity LCS / indel^2).
+ * Arrays hold k entries; NULL ones are skipped. */
+int famsa_mst_result(const famsa_mst_t* mst, uint32_t* u, uint32_t* v, int64_t* lcs, int64_t* indel2,
+                     uint32_t* nedges);
+void famsa_mst_destroy(famsa_mst_t* mst);
+
+/* ------------------------------------------------------------------------
  * Serving: similarity jobs (each one family) are admitted while their device
  * footprint fits the budget, kept resident, and batched together: every
  * scheduler step gathers the next tiles of all admitted jobs into one launch

@@ -97,6 +97,14 @@ def lib():
         L.famsa_slink_rows_done.restype = ctypes.c_uint32
         L.famsa_slink_destroy.argtypes = [vp]
         L.famsa_slink_destroy.restype = None
+        L.famsa_mst_create.argtypes = [u32p, ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(vp)]
+        L.famsa_mst_create.restype = ctypes.c_int
+        L.famsa_mst_consume.argtypes = [vp, ctypes.POINTER(Tile)]
+        L.famsa_mst_consume.restype = ctypes.c_int
+        L.famsa_mst_result.argtypes = [vp, u32p, u32p, i64p, i64p, u32p]
+        L.famsa_mst_result.restype = ctypes.c_int
+        L.famsa_mst_destroy.argtypes = [vp]
+        L.famsa_mst_destroy.restype = None
         L.famsa_lcs_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.famsa_lcs_server_create.restype = ctypes.c_int
         L.famsa_lcs_server_submit.argtypes = [vp, u8p, u64p, ctypes.c_uint32, u32p]
@@ -278,6 +286,45 @@ class SLink:
     def close(self):
         if getattr(self, "handle", None):
             lib().famsa_slink_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mst:
+    """GPU single-linkage consumer (famsa_mst_*): feed device tiles."""
+
+    def __init__(self, lengths: np.ndarray, device: int = 0):
+        self._len = np.ascontiguousarray(lengths, dtype=np.uint32)
+        h = ctypes.c_void_p()
+        check(lib().famsa_mst_create(_ptr(self._len, ctypes.c_uint32) if self._len.size else None,
+                                     self._len.size, device, ctypes.byref(h)))
+        self.handle = h
+        self.k = int(self._len.size)
+
+    @staticmethod
+    def consume_fn():
+        return ctypes.cast(lib().famsa_mst_consume, TILE_FN)
+
+    def result(self):
+        n = max(self.k, 1)
+        u = np.zeros(n, np.uint32)
+        v = np.zeros(n, np.uint32)
+        L = np.zeros(n, np.int64)
+        D = np.zeros(n, np.int64)
+        ne = ctypes.c_uint32()
+        check(lib().famsa_mst_result(self.handle, _ptr(u, ctypes.c_uint32), _ptr(v, ctypes.c_uint32),
+                                     _ptr(L, ctypes.c_int64), _ptr(D, ctypes.c_int64), ctypes.byref(ne)))
+        m = int(ne.value)
+        return u[:m], v[:m], L[:m], D[:m]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().famsa_mst_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,115 @@
+"""GPU single-linkage consumer (famsa_mst_*): the maximum spanning tree it
+keeps from device tiles equals the unique tie-broken maximum spanning tree of
+the oracle's exact similarities (Kruskal, most similar first, ties by (u, v)),
+and its merge heights and cophenetic similarities equal the oracle's single
+linkage; on a larger family its merge heights equal the host SLINK's."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_06958_amd import binding as B
+from paper_1603_06958_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_tree(b, **opt):
+    m = B.Mst(b.lengths())
+    with B.Plan.from_batch(b, flags=B.DEVICE_TILES | opt.pop("flags", 0), **opt) as p:
+        p.run_native(B.Mst.consume_fn(), m.handle)
+    u, v, L, D = m.result()
+    m.close()
+    return u, v, L, D
+
+
+def sim(L, D):
+    return oracle.INF if D == 0 else Fraction(int(L), int(D))
+
+
+def oracle_tree(M, lengths):
+    k = M.shape[0]
+    edges = []
+    for i in range(k):
+        for j in range(i + 1, k):
+            edges.append((oracle.similarity(int(M[i, j]), int(lengths[i]), int(lengths[j])), i, j))
+    # most similar first; equal similarities by (u, v) ascending
+    edges.sort(key=lambda e: (-1 if e[0] == oracle.INF else 0, -e[0] if e[0] != oracle.INF else 0, e[1], e[2]))
+    parent = list(range(k))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    tree = []
+    for s, i, j in edges:
+        a, c = find(i), find(j)
+        if a != c:
+            parent[a] = c
+            tree.append((i, j, s))
+    return tree
+
+
+def cophenetic_from_tree(k, edges):
+    order = sorted(edges, key=lambda e: (-1 if e[2] == oracle.INF else 0, -e[2] if e[2] != oracle.INF else 0))
+    parent = list(range(k))
+    members = {i: [i] for i in range(k)}
+
+    def find(x):
+        while parent[x] != x:
+            x = parent[x]
+        return x
+
+    C = np.empty((k, k), dtype=object)
+    for i in range(k):
+        C[i, i] = oracle.INF
+    for u, v, s in order:
+        a, c = find(u), find(v)
+        for x in members[a]:
+            for y in members[c]:
+                C[x, y] = C[y, x] = s
+        parent[a] = c
+        members[c] += members.pop(a)
+    return C
+
+
+@pytest.mark.parametrize("seed,k,lo,hi,sigma,R,flags", [
+    (1, 40, 0, 30, 3, 7, 0), (2, 90, 5, 120, 20, 1024, 0), (3, 65, 1, 8, 2, 5, B.DESCENDING),
+    (4, 130, 20, 300, 4, 64, 0), (5, 2, 3, 3, 2, 1, 0), (6, 1, 3, 3, 2, 1, 0), (7, 70, 0, 40, 20, 16, B.NO_GRAPH)])
+def test_tree_matches_oracle(seed, k, lo, hi, sigma, R, flags):
+    b = inputs.random_family(k, lo, hi, seed, alphabet=sigma)
+    if seed == 3:  # identical and empty sequences: similarity +inf, many ties
+        seqs = [b.seq(i) for i in range(k)]
+        seqs[5] = seqs[6].copy()
+        seqs[9] = seqs[6].copy()
+        seqs[7] = np.zeros(0, np.uint8)
+        seqs[8] = np.zeros(0, np.uint8)
+        b = inputs.from_sequences(seqs)
+    M = oracle.full_matrix(b.codes, b.seq_off, 0, k)
+    L = b.lengths()
+    u, v, l, d = gpu_tree(b, tile_rows=R, alphabet_size=max(sigma, 2), flags=flags)
+    assert len(u) == k - 1
+    got = sorted((int(a), int(c), sim(x, y)) for a, c, x, y in zip(u, v, l, d))
+    for a, c, x in got:
+        assert int(M[a, c]) == l[list(zip(u, v)).index((a, c))]
+    want = sorted(oracle_tree(M, L))
+    assert got == want
+    h_ref, c_ref = oracle.single_linkage(M, L)
+    assert sorted(s for _, _, s in got) == sorted(h_ref)
+    assert (cophenetic_from_tree(k, got) == c_ref).all()
+
+
+def test_heights_match_host_slink_c2_like():
+    b = inputs.c2(k=3000)
+    k = b.nseq
+    u, v, l, d = gpu_tree(b, tile_rows=256, step_values=200_000)
+    s = B.SLink(b.lengths())
+    with B.Plan.from_batch(b, tile_rows=256, flags=B.DESCENDING) as p:
+        p.run_native(B.SLink.consume_fn(), s.handle)
+    pi, num, den = s.result()
+    slink_h = sorted(sim(n, q) for n, q in zip(num, den) if not (n == -1 and q == 0))
+    assert len(u) == k - 1
+    assert sorted(sim(x, y) for x, y in zip(l, d)) == slink_h
