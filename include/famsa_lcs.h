@@ -209,23 +209,28 @@ void famsa_slink_destroy(famsa_slink_t* s);
  * pointer representation this consumer keeps that tree on the device: after
  * each device tile (FAMSA_LCS_DEVICE_TILES) it replaces its forest with the
  * maximum spanning forest of the forest plus the tile's pairs (Boruvka
- * rounds on the GPU).  Memory is O(k) on the device; tiles may come in any
- * order.  Similarities are ordered exactly; equal similarities are ordered
- * by the pair (u, v), u < v, so the tree is unique.
+ * rounds on the GPU, one pass over the tile per round).  Device memory is
+ * O(k) plus per-round partial results of about k * R / 50 entries for tiles
+ * of R rows (R <= 65535); tiles may come in any order.  Similarities are
+ * ordered exactly; equal similarities are ordered by the pair (u, v), u < v,
+ * so the tree is unique.
  * ------------------------------------------------------------------------ */
 typedef struct famsa_mst_s famsa_mst_t;
 
 /* lengths: the k sequence lengths of the family (copied to `device`). */
 int famsa_mst_create(const uint32_t* lengths, uint32_t k, int device, famsa_mst_t** out);
 /* A famsa_lcs_tile_fn for device tiles: pass the famsa_mst_t* as `user`.
- * Orders its GPU work on tile->stream and returns when the tile is merged
- * (nonzero on a bad tile or a HIP error). */
+ * Orders its GPU work on tile->stream and returns once that work has
+ * finished reading the tile (nonzero on a bad tile or a HIP error); calls on
+ * one famsa_mst_t must not overlap. */
 int famsa_mst_consume(void* mst, const famsa_lcs_tile* tile);
 /* The forest's edges (k-1 of them once every pair has been seen): endpoints
  * u < v (family-local), their LCS and indel^2 (similarity LCS / indel^2).
  * Arrays hold k entries; NULL ones are skipped. */
 int famsa_mst_result(const famsa_mst_t* mst, uint32_t* u, uint32_t* v, int64_t* lcs, int64_t* indel2,
                      uint32_t* nedges);
+/* Tiles merged so far and the Boruvka rounds that joined components. */
+int famsa_mst_get_stats(const famsa_mst_t* mst, uint64_t* tiles, uint64_t* rounds);
 void famsa_mst_destroy(famsa_mst_t* mst);
 
 /* ------------------------------------------------------------------------

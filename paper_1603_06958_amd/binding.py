@@ -103,6 +103,8 @@ def lib():
         L.famsa_mst_consume.restype = ctypes.c_int
         L.famsa_mst_result.argtypes = [vp, u32p, u32p, i64p, i64p, u32p]
         L.famsa_mst_result.restype = ctypes.c_int
+        L.famsa_mst_get_stats.argtypes = [vp, u64p, u64p]
+        L.famsa_mst_get_stats.restype = ctypes.c_int
         L.famsa_mst_destroy.argtypes = [vp]
         L.famsa_mst_destroy.restype = None
         L.famsa_lcs_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(vp)]
@@ -321,6 +323,11 @@ class Mst:
                                      _ptr(L, ctypes.c_int64), _ptr(D, ctypes.c_int64), ctypes.byref(ne)))
         m = int(ne.value)
         return u[:m], v[:m], L[:m], D[:m]
+
+    def stats(self):
+        t, r = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().famsa_mst_get_stats(self.handle, ctypes.byref(t), ctypes.byref(r)))
+        return int(t.value), int(r.value)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -55,126 +55,220 @@ struct MstDev {
   uint64_t* vkey;     // best outgoing edge per vertex: key, id, LCS
   uint64_t* vid;
   int32_t* vL;
-  uint64_t* wkey;     // best forest edge per vertex (merged into vkey/vid/vL after the forest pass)
+  uint64_t* wkey;     // best forest edge per vertex (merged into vkey/vid/vL)
   uint64_t* wid;
   int32_t* wL;
   uint64_t* ckey;     // best outgoing edge per component
   uint64_t* cid;
   int32_t* cL;
-  const uint32_t* fu;  // current forest edges
+  uint64_t* pkey;     // row partials: best edge of each (tile row, column block)
+  uint64_t* pid;
+  int32_t* pL;
+  uint64_t* qkey;     // column partials: best edge of each (row slice, column)
+  uint64_t* qid;
+  int32_t* qL;
+  const uint32_t* fu;  // current forest edges (ctl->nf of them)
   const uint32_t* fv;
   const int32_t* fL;
-  uint32_t nf;
-  uint32_t* nu;        // new forest edges
+  uint32_t* nu;        // new forest edges (ctl->nnew of them)
   uint32_t* nv;
   int32_t* nL;
-  uint32_t* counters;  // [0] new forest size, [1] hooks this round
+  struct Ctl {
+    uint32_t nf;      // edges in the current forest
+    uint32_t nnew;    // edges in the new forest
+    uint32_t hooks;   // hooks in this round
+    uint32_t done;    // no component has an outgoing edge: later rounds do nothing
+    uint64_t rounds;  // rounds that did work, over all tiles
+  }* ctl;
 };
 
-__global__ void mst_reset_vertices(MstDev m) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.k) return;
-  m.vkey[v] = 0;
-  m.vid[v] = ~0ull;
-  m.vL[v] = 0;
-  m.wkey[v] = 0;
-  m.wid[v] = ~0ull;
-  m.wL[v] = 0;
-  m.ckey[v] = 0;
-  m.cid[v] = ~0ull;
+// The scan: a block covers 256 columns (four per lane) and a slice of 64
+// tile rows, split over its four waves.
+constexpr uint32_t kScanCols = 256;
+constexpr uint32_t kScanSlice = 64;
+constexpr uint32_t kScanWaves = 4;
+
+// Values before tile row i (rows r0.. of the upper triangle, k - 1 - t per row t).
+__device__ __forceinline__ uint64_t row_off(uint64_t k, uint32_t r0, uint32_t i) {
+  const uint64_t n = i - r0;
+  return n * (k - 1) - ((uint64_t)r0 + i - 1) * n / 2;
 }
 
-__global__ void mst_init_components(MstDev m) {
+__device__ __forceinline__ void take(uint64_t& bk, uint64_t& bi, int32_t& bL, uint64_t k2, uint64_t i2, int32_t L2) {
+  if (better(k2, i2, bk, bi)) {
+    bk = k2;
+    bi = i2;
+    bL = L2;
+  }
+}
+
+// Wave-wide best of (key, id, L); every lane gets the result.
+__device__ __forceinline__ void wave_best(uint64_t& bk, uint64_t& bi, int32_t& bL) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t k2 = __shfl_xor(bk, d, 64);
+    const uint64_t i2 = __shfl_xor(bi, d, 64);
+    const int32_t L2 = __shfl_xor(bL, d, 64);
+    take(bk, bi, bL, k2, i2, L2);
+  }
+}
+
+__global__ void mst_tile_begin(MstDev m) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) {
+    m.ctl->done = 0;
+    m.ctl->hooks = 0;
+    m.ctl->nnew = 0;
+  }
   if (v >= m.k) return;
   m.comp[v] = v;
   m.parent[v] = v;
 }
 
-// Row pass: one block per tile row i, best edge (i, j), j > i, leaving i's component.
-__global__ __launch_bounds__(256) void mst_rows(MstDev m, const int32_t* __restrict__ tile, uint32_t r0, uint32_t r1) {
-  const uint32_t i = r0 + blockIdx.x;
-  if (i >= r1) return;
+// One pass over the tile per round, in small blocks that fit beside the
+// LCS kernels.  Block (bx, sy) covers columns [256 bx, 256 bx + 256) (four
+// per lane) and the 64 tile rows of slice sy that have a column after them
+// in the block; each element (i, j) whose ends lie in different components is
+// a candidate for both ends.  A row's best over the block's columns is a wave
+// reduction, stored as partial (row, bx); a column's best over the slice's
+// rows is reduced over the four waves in LDS and stored as partial (sy, j).
+__global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restrict__ tile, uint32_t r0, uint32_t r1,
+                                                uint32_t nblk) {
+  if (m.ctl->done) return;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t jb = blockIdx.x * kScanCols;
   const uint64_t k = m.k;
-  const uint64_t off = (i - r0) * (k - 1) - ((uint64_t)(r0 + i - 1) * (i - r0)) / 2;  // rows before i in the tile
-  const uint32_t ci = m.comp[i], li = m.len[i];
-  uint64_t bk = 0, bi = ~0ull;
-  int32_t bL = 0;
-  for (uint32_t j = i + 1 + threadIdx.x; j < m.k; j += blockDim.x) {
-    if (m.comp[j] == ci) continue;
-    const int32_t L = tile[off + (j - i - 1)];
-    const uint64_t key = sim_key(L, li, m.len[j]);
-    const uint64_t id = (uint64_t)i * k + j;
-    if (better(key, id, bk, bi)) {
-      bk = key;
-      bi = id;
-      bL = L;
+  uint64_t ck[4], cid[4];
+  int32_t cL[4];
+  uint32_t cc[4], cl[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    ck[c] = 0;
+    cid[c] = ~0ull;
+    cL[c] = 0;
+    const uint32_t j = jb + 64u * c + lane;
+    cc[c] = j < m.k ? m.comp[j] : 0u;
+    cl[c] = j < m.k ? m.len[j] : 0u;
+  }
+  const uint32_t i0 = r0 + blockIdx.y * kScanSlice;
+  const uint32_t iend = min(min(r1, i0 + kScanSlice), jb + kScanCols - 1u);  // rows with a column of the block after them
+  for (uint32_t i = i0 + wave; i < iend; i += kScanWaves) {
+    const uint32_t ci = m.comp[i], li = m.len[i];
+    const uint64_t off = row_off(k, r0, i);  // LCS(i, j) at off + j - i - 1
+    int32_t L[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t j = jb + 64u * c + lane;
+      L[c] = (j > i && j < m.k) ? tile[off + (j - i - 1u)] : 0;
+    }
+    uint64_t rk = 0, ri = ~0ull;
+    int32_t rL = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t j = jb + 64u * c + lane;
+      if (j > i && j < m.k && cc[c] != ci) {
+        const uint64_t key = sim_key(L[c], li, cl[c]);
+        const uint64_t id = (uint64_t)i * k + j;
+        take(ck[c], cid[c], cL[c], key, id, L[c]);
+        take(rk, ri, rL, key, id, L[c]);
+      }
+    }
+    wave_best(rk, ri, rL);
+    if (lane == 0) {
+      const uint64_t p = (uint64_t)(i - r0) * nblk + blockIdx.x;
+      m.pkey[p] = rk;
+      m.pid[p] = ri;
+      m.pL[p] = rL;
     }
   }
-  __shared__ uint64_t sk[256], si[256];
-  __shared__ int32_t sL[256];
-  sk[threadIdx.x] = bk;
-  si[threadIdx.x] = bi;
-  sL[threadIdx.x] = bL;
-  __syncthreads();
-  for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s && better(sk[threadIdx.x + s], si[threadIdx.x + s], sk[threadIdx.x], si[threadIdx.x])) {
-      sk[threadIdx.x] = sk[threadIdx.x + s];
-      si[threadIdx.x] = si[threadIdx.x + s];
-      sL[threadIdx.x] = sL[threadIdx.x + s];
+  __shared__ uint64_t sk[kScanWaves / 2][kScanCols], si[kScanWaves / 2][kScanCols];
+  __shared__ int32_t sL[kScanWaves / 2][kScanCols];
+  for (uint32_t h = kScanWaves / 2; h > 0; h >>= 1) {
+    if (wave >= h && wave < 2 * h) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sk[wave - h][64 * c + lane] = ck[c];
+        si[wave - h][64 * c + lane] = cid[c];
+        sL[wave - h][64 * c + lane] = cL[c];
+      }
+    }
+    __syncthreads();
+    if (wave < h) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        take(ck[c], cid[c], cL[c], sk[wave][64 * c + lane], si[wave][64 * c + lane], sL[wave][64 * c + lane]);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && better(sk[0], si[0], m.vkey[i], m.vid[i])) {
-    m.vkey[i] = sk[0];
-    m.vid[i] = si[0];
-    m.vL[i] = sL[0];
+  if (wave == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t j = jb + 64u * c + lane;
+      if (j >= m.k) continue;
+      const uint64_t q = (uint64_t)blockIdx.y * k + j;
+      m.qkey[q] = ck[c];
+      m.qid[q] = cid[c];
+      m.qL[q] = cL[c];
+    }
   }
 }
 
-// Column pass: one thread per column j > r0, best edge (i, j) over tile rows i < j.
-__global__ __launch_bounds__(256) void mst_cols(MstDev m, const int32_t* __restrict__ tile, uint32_t r0, uint32_t r1) {
-  const uint32_t j = r0 + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+// Column results and per-round reset: vertex j takes the best of its column
+// partials over the row slices; its forest and component slots are cleared.
+__global__ void mst_col_reduce(MstDev m, uint32_t nslice) {
+  if (m.ctl->done) return;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.k) return;
-  const uint64_t k = m.k;
-  const uint32_t cj = m.comp[j], lj = m.len[j];
-  uint64_t bk = m.vkey[j], bi = m.vid[j];
-  int32_t bL = m.vL[j];
-  const uint32_t iend = j < r1 ? j : r1;
-  uint64_t off = 0;  // start of row i in the tile
-  for (uint32_t i = r0; i < iend; ++i) {
-    if (m.comp[i] != cj) {
-      const int32_t L = tile[off + (j - i - 1)];
-      const uint64_t key = sim_key(L, m.len[i], lj);
-      const uint64_t id = (uint64_t)i * k + j;
-      if (better(key, id, bk, bi)) {
-        bk = key;
-        bi = id;
-        bL = L;
-      }
-    }
-    off += k - 1 - i;
+  uint64_t bk = 0, bi = ~0ull;
+  int32_t bL = 0;
+  for (uint32_t y = 0; y < nslice; ++y) {
+    const uint64_t q = (uint64_t)y * m.k + j;
+    take(bk, bi, bL, m.qkey[q], m.qid[q], m.qL[q]);
   }
   m.vkey[j] = bk;
   m.vid[j] = bi;
   m.vL[j] = bL;
+  m.wkey[j] = 0;
+  m.wid[j] = ~0ull;
+  m.wL[j] = 0;
+  m.ckey[j] = 0;
+  m.cid[j] = ~0ull;
+}
+
+// Row results: tile row i reduces its partials over the blocks that hold a
+// column after it, and merges them into its candidate.
+__global__ __launch_bounds__(64) void mst_row_reduce(MstDev m, uint32_t r0, uint32_t nblk) {
+  if (m.ctl->done) return;
+  const uint32_t i = r0 + blockIdx.x;
+  uint64_t bk = 0, bi = ~0ull;
+  int32_t bL = 0;
+  const uint64_t base = (uint64_t)blockIdx.x * nblk;
+  for (uint32_t b = (i + 1u) / kScanCols + threadIdx.x; b < nblk; b += 64u)
+    take(bk, bi, bL, m.pkey[base + b], m.pid[base + b], m.pL[base + b]);
+  wave_best(bk, bi, bL);
+  if (threadIdx.x == 0) {
+    take(bk, bi, bL, m.vkey[i], m.vid[i], m.vL[i]);
+    m.vkey[i] = bk;
+    m.vid[i] = bi;
+    m.vL[i] = bL;
+  }
 }
 
 // Forest edges: candidates for both ends, gathered in the w* slots in three
-// phases (key, id, LCS), then merged with the tile's candidates.
+// phases (key, id, LCS).
 __global__ void mst_forest_key(MstDev m) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m.nf) return;
+  if (m.ctl->done || e >= m.ctl->nf) return;
   const uint32_t u = m.fu[e], v = m.fv[e];
   if (m.comp[u] == m.comp[v]) return;
   const uint64_t key = sim_key(m.fL[e], m.len[u], m.len[v]);
-  atomicMax((unsigned long long*)&m.wkey[u], (unsigned long long)key);
-  atomicMax((unsigned long long*)&m.wkey[v], (unsigned long long)key);
+  if (key > m.wkey[u]) atomicMax((unsigned long long*)&m.wkey[u], (unsigned long long)key);
+  if (key > m.wkey[v]) atomicMax((unsigned long long*)&m.wkey[v], (unsigned long long)key);
 }
 
 __global__ void mst_forest_id(MstDev m) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m.nf) return;
+  if (m.ctl->done || e >= m.ctl->nf) return;
   const uint32_t u = m.fu[e], v = m.fv[e];
   if (m.comp[u] == m.comp[v]) return;
   const uint64_t key = sim_key(m.fL[e], m.len[u], m.len[v]);
@@ -185,7 +279,7 @@ __global__ void mst_forest_id(MstDev m) {
 
 __global__ void mst_forest_L(MstDev m) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m.nf) return;
+  if (m.ctl->done || e >= m.ctl->nf) return;
   const uint32_t u = m.fu[e], v = m.fv[e];
   if (m.comp[u] == m.comp[v]) return;
   const uint64_t id = (uint64_t)u * m.k + v;
@@ -193,32 +287,35 @@ __global__ void mst_forest_L(MstDev m) {
   if (m.wid[v] == id) m.wL[v] = m.fL[e];
 }
 
-__global__ void mst_forest_merge(MstDev m) {
+// Each vertex's candidate (tile pass results already in v*) takes its forest
+// edge, and offers itself to its component's maximum.  A plain read first
+// skips most atomics: once a component holds a large key few vertices beat it.
+__global__ void mst_vertex_merge(MstDev m) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.k || m.wkey[v] == 0) return;
-  if (better(m.wkey[v], m.wid[v], m.vkey[v], m.vid[v])) {
-    m.vkey[v] = m.wkey[v];
-    m.vid[v] = m.wid[v];
-    m.vL[v] = m.wL[v];
+  if (m.ctl->done || v >= m.k) return;
+  uint64_t bk = m.vkey[v], bi = m.vid[v];
+  int32_t bL = m.vL[v];
+  if (m.wkey[v]) {
+    take(bk, bi, bL, m.wkey[v], m.wid[v], m.wL[v]);
+    m.vkey[v] = bk;
+    m.vid[v] = bi;
+    m.vL[v] = bL;
   }
-}
-
-__global__ void mst_comp_key(MstDev m) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.k || m.vkey[v] == 0) return;
-  atomicMax((unsigned long long*)&m.ckey[m.comp[v]], (unsigned long long)m.vkey[v]);
+  if (bk == 0) return;
+  uint64_t* slot = &m.ckey[m.comp[v]];
+  if (bk > *slot) atomicMax((unsigned long long*)slot, (unsigned long long)bk);
 }
 
 __global__ void mst_comp_id(MstDev m) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.k || m.vkey[v] == 0) return;
+  if (m.ctl->done || v >= m.k || m.vkey[v] == 0) return;
   const uint32_t c = m.comp[v];
   if (m.vkey[v] == m.ckey[c]) atomicMin((unsigned long long*)&m.cid[c], (unsigned long long)m.vid[v]);
 }
 
 __global__ void mst_comp_L(MstDev m) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.k || m.vkey[v] == 0) return;
+  if (m.ctl->done || v >= m.k || m.vkey[v] == 0) return;
   const uint32_t c = m.comp[v];
   if (m.vkey[v] == m.ckey[c] && m.vid[v] == m.cid[c]) m.cL[c] = m.vL[v];  // one vertex per component matches
 }
@@ -228,17 +325,17 @@ __global__ void mst_comp_L(MstDev m) {
 // the smaller.  Each hook adds its edge to the new forest.
 __global__ void mst_hook(MstDev m) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m.k || m.comp[c] != c || m.ckey[c] == 0) return;
+  if (m.ctl->done || c >= m.k || m.comp[c] != c || m.ckey[c] == 0) return;
   const uint64_t id = m.cid[c];
   const uint32_t u = (uint32_t)(id / m.k), v = (uint32_t)(id % m.k);
   const uint32_t d = m.comp[u] == c ? m.comp[v] : m.comp[u];
   if (m.cid[d] == id && c < d) return;  // mutual choice: d hooks onto c
   m.parent[c] = d;
-  const uint32_t slot = atomicAdd(&m.counters[0], 1u);
+  const uint32_t slot = atomicAdd(&m.ctl->nnew, 1u);
   m.nu[slot] = u;
   m.nv[slot] = v;
   m.nL[slot] = m.cL[c];
-  atomicAdd(&m.counters[1], 1u);
+  atomicAdd(&m.ctl->hooks, 1u);
 }
 
 // Every component follows its hook chain to the root (chains are acyclic:
@@ -247,20 +344,34 @@ __global__ void mst_hook(MstDev m) {
 // entries further up the same chain.
 __global__ void mst_jump(MstDev m) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m.k) return;
+  if (m.ctl->done || c >= m.k) return;
   uint32_t r = m.parent[c];
   while (m.parent[r] != r) r = m.parent[r];
   m.parent[c] = r;
 }
 
+// Relabel every vertex; the first thread also ends the round: a round
+// without hooks finishes the tile (its relabelling changes nothing, so blocks
+// that see the flag early lose nothing).
 __global__ void mst_relabel(MstDev m) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.k) return;
+  if (m.ctl->done || v >= m.k) return;
   m.comp[v] = m.parent[m.comp[v]];
+  if (v == 0) {
+    if (m.ctl->hooks == 0) {
+      m.ctl->done = 1;
+    } else {
+      m.ctl->rounds += 1;
+      m.ctl->hooks = 0;
+    }
+  }
 }
 
-__global__ void mst_zero(uint32_t* p, uint32_t n) {
-  if (threadIdx.x < n) p[threadIdx.x] = 0;
+// The new forest becomes the current one (the host swaps the arrays).
+__global__ void mst_tile_end(MstDev m) {
+  if (threadIdx.x != 0) return;
+  m.ctl->nf = m.ctl->nnew;
+  m.ctl->nnew = 0;
 }
 
 }  // namespace famsa
@@ -270,10 +381,12 @@ using namespace famsa;
 struct famsa_mst_s {
   uint32_t k = 0;
   int device = 0;
-  DevMem len, comp, parent, vkey, vid, vL, wkey, wid, wL, ckey, cid, cL, fu, fv, fL, nu, nv, nL, counters;
-  PinMem hcount;
-  uint32_t nf = 0;
-  uint64_t tiles = 0, rounds = 0;
+  DevMem len, comp, parent, vkey, vid, vL, wkey, wid, wL, ckey, cid, cL, pkey, pid, pL, qkey, qid, qL;
+  DevMem fu, fv, fL, nu, nv, nL, ctl;
+  uint64_t part_cap = 0;   // row partials the p* arrays hold
+  uint32_t slice_cap = 0;  // row slices the q* arrays hold
+  PinMem hctl;
+  uint64_t tiles = 0;
   MstDev view() {
     MstDev m;
     m.len = len.as<uint32_t>();
@@ -289,60 +402,87 @@ struct famsa_mst_s {
     m.ckey = ckey.as<uint64_t>();
     m.cid = cid.as<uint64_t>();
     m.cL = cL.as<int32_t>();
+    m.pkey = pkey.as<uint64_t>();
+    m.pid = pid.as<uint64_t>();
+    m.pL = pL.as<int32_t>();
+    m.qkey = qkey.as<uint64_t>();
+    m.qid = qid.as<uint64_t>();
+    m.qL = qL.as<int32_t>();
     m.fu = fu.as<uint32_t>();
     m.fv = fv.as<uint32_t>();
     m.fL = fL.as<int32_t>();
-    m.nf = nf;
     m.nu = nu.as<uint32_t>();
     m.nv = nv.as<uint32_t>();
     m.nL = nL.as<int32_t>();
-    m.counters = counters.as<uint32_t>();
+    m.ctl = ctl.as<MstDev::Ctl>();
     return m;
   }
   int merge_tile(const famsa_lcs_tile* t, hipStream_t s);
+  int read_ctl(MstDev::Ctl* out, hipStream_t s);
 };
 
-static inline dim3 grid_for(uint64_t n, uint32_t b = 256) { return dim3((uint32_t)((n + b - 1) / b)); }
+static inline dim3 grid_for(uint64_t n, uint32_t b = 256) { return dim3((uint32_t)std::max<uint64_t>(1, (n + b - 1) / b)); }
 
+int famsa_mst_s::read_ctl(MstDev::Ctl* out, hipStream_t s) {
+  FAMSA_HIP(hipMemcpyAsync(hctl.p, ctl.p, sizeof(MstDev::Ctl), hipMemcpyDeviceToHost, s));
+  FAMSA_HIP(hipStreamSynchronize(s));
+  memcpy(out, hctl.p, sizeof(MstDev::Ctl));
+  return 0;
+}
+
+// Boruvka rounds are queued in batches without waiting: every kernel of a
+// round after the last useful one returns at once (the `done` flag), so the
+// host only checks after each batch.  Borůvka needs at most ceil(log2 k) + 1
+// rounds, and few tiles need more than the first batch.
 int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
   const uint32_t r0 = t->row_begin, r1 = t->row_end;
-  const dim3 gk = grid_for(k);
-  uint32_t* hc = hcount.as<uint32_t>();
-  MstDev m = view();
-  hipLaunchKernelGGL(mst_init_components, gk, dim3(256), 0, s, m);
-  hipLaunchKernelGGL(mst_zero, dim3(1), dim3(64), 0, s, m.counters, 4u);
-  for (;;) {
-    m = view();
-    hipLaunchKernelGGL(mst_reset_vertices, gk, dim3(256), 0, s, m);
-    if (t->count && r1 > r0) {
-      hipLaunchKernelGGL(mst_rows, dim3(r1 - r0), dim3(256), 0, s, m, t->lcs, r0, r1);
-      if (r0 + 1 < k) hipLaunchKernelGGL(mst_cols, grid_for(k - r0 - 1), dim3(256), 0, s, m, t->lcs, r0, r1);
+  const bool has_tile = t->count && r1 > r0;
+  if (r1 - r0 > 65535u) return set_error(FAMSA_LCS_EINVAL, "tiles of more than 65535 rows are not supported");
+  const uint32_t nblk = (uint32_t)((k + kScanCols - 1) / kScanCols);
+  const uint32_t nslice = has_tile ? (r1 - r0 + kScanSlice - 1) / kScanSlice : 0;
+  if (has_tile && ((uint64_t)nblk * (r1 - r0) > part_cap || nslice > slice_cap)) {
+    FAMSA_HIP(hipStreamSynchronize(s));  // the old partials may still be in use
+    int rc;
+    if ((uint64_t)nblk * (r1 - r0) > part_cap) {
+      part_cap = (uint64_t)nblk * (r1 - r0);
+      if ((rc = pkey.alloc(part_cap * 8)) || (rc = pid.alloc(part_cap * 8)) || (rc = pL.alloc(part_cap * 4))) return rc;
     }
-    if (nf) {
-      hipLaunchKernelGGL(mst_forest_key, grid_for(nf), dim3(256), 0, s, m);
-      hipLaunchKernelGGL(mst_forest_id, grid_for(nf), dim3(256), 0, s, m);
-      hipLaunchKernelGGL(mst_forest_L, grid_for(nf), dim3(256), 0, s, m);
-      hipLaunchKernelGGL(mst_forest_merge, gk, dim3(256), 0, s, m);
+    if (nslice > slice_cap) {
+      slice_cap = nslice;
+      const uint64_t n = (uint64_t)slice_cap * k;
+      if ((rc = qkey.alloc(n * 8)) || (rc = qid.alloc(n * 8)) || (rc = qL.alloc(n * 4))) return rc;
     }
-    hipLaunchKernelGGL(mst_comp_key, gk, dim3(256), 0, s, m);
-    hipLaunchKernelGGL(mst_comp_id, gk, dim3(256), 0, s, m);
-    hipLaunchKernelGGL(mst_comp_L, gk, dim3(256), 0, s, m);
-    hipLaunchKernelGGL(mst_hook, gk, dim3(256), 0, s, m);
-    FAMSA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(mst_jump, gk, dim3(256), 0, s, m);
-    hipLaunchKernelGGL(mst_relabel, gk, dim3(256), 0, s, m);
-    FAMSA_HIP(hipGetLastError());
-    FAMSA_HIP(hipMemcpyAsync(hc, m.counters, 8, hipMemcpyDeviceToHost, s));
-    FAMSA_HIP(hipStreamSynchronize(s));
-    ++rounds;
-    const uint32_t hooks = hc[1];
-    hipLaunchKernelGGL(mst_zero, dim3(1), dim3(64), 0, s, m.counters + 1, 1u);  // hooks of the next round
-    if (hooks == 0) break;
   }
-  // the new forest replaces the old one
-  FAMSA_HIP(hipMemcpyAsync(hc, m.counters, 4, hipMemcpyDeviceToHost, s));
-  FAMSA_HIP(hipStreamSynchronize(s));
-  nf = hc[0];
+  const MstDev m = view();
+  const dim3 gk = grid_for(k);
+  hipLaunchKernelGGL(mst_tile_begin, gk, dim3(256), 0, s, m);
+  const uint32_t kmax_rounds = 2 + (uint32_t)ceil(log2((double)std::max<uint32_t>(k, 2)));
+  uint32_t queued = 0;
+  for (uint32_t batch = 6;; batch = 2) {
+    for (uint32_t r = 0; r < batch; ++r) {
+      if (has_tile) hipLaunchKernelGGL(mst_scan, dim3(nblk, nslice), dim3(64 * kScanWaves), 0, s, m, t->lcs, r0, r1, nblk);
+      hipLaunchKernelGGL(mst_col_reduce, gk, dim3(256), 0, s, m, nslice);
+      if (has_tile) hipLaunchKernelGGL(mst_row_reduce, dim3(r1 - r0), dim3(64), 0, s, m, r0, nblk);
+      hipLaunchKernelGGL(mst_forest_key, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_forest_id, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_forest_L, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_vertex_merge, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_comp_id, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_comp_L, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_hook, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_jump, gk, dim3(256), 0, s, m);
+      hipLaunchKernelGGL(mst_relabel, gk, dim3(256), 0, s, m);
+      FAMSA_HIP(hipGetLastError());
+    }
+    queued += batch;
+    MstDev::Ctl c;
+    int rc = read_ctl(&c, s);
+    if (rc) return rc;
+    if (c.done) break;
+    if (queued > kmax_rounds) return set_error(FAMSA_LCS_EDEVICE, "spanning forest did not converge in %u rounds", queued);
+  }
+  hipLaunchKernelGGL(mst_tile_end, dim3(1), dim3(64), 0, s, m);
+  FAMSA_HIP(hipGetLastError());
   std::swap(fu.p, nu.p);
   std::swap(fv.p, nv.p);
   std::swap(fL.p, nL.p);
@@ -381,13 +521,14 @@ int famsa_mst_create(const uint32_t* lengths, uint32_t k, int device, famsa_mst_
       (rc = m->ckey.alloc(n * 8)) || (rc = m->cid.alloc(n * 8)) || (rc = m->cL.alloc(n * 4)) ||
       (rc = m->fu.alloc(n * 4)) || (rc = m->fv.alloc(n * 4)) || (rc = m->fL.alloc(n * 4)) ||
       (rc = m->nu.alloc(n * 4)) || (rc = m->nv.alloc(n * 4)) || (rc = m->nL.alloc(n * 4)) ||
-      (rc = m->counters.alloc(16)) || (rc = m->hcount.alloc(16))) {
+      (rc = m->ctl.alloc(sizeof(MstDev::Ctl))) || (rc = m->hctl.alloc(sizeof(MstDev::Ctl)))) {
     delete m;
     return rc;
   }
-  if (k && hipMemcpy(m->len.p, lengths, (size_t)k * 4, hipMemcpyHostToDevice) != hipSuccess) {
+  if ((k && hipMemcpy(m->len.p, lengths, (size_t)k * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemset(m->ctl.p, 0, sizeof(MstDev::Ctl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     delete m;
-    return set_error(FAMSA_LCS_EDEVICE, "copying lengths failed");
+    return set_error(FAMSA_LCS_EDEVICE, "initialising the forest failed");
   }
   *out = m;
   return 0;
@@ -408,7 +549,9 @@ int famsa_mst_result(const famsa_mst_t* m, uint32_t* u, uint32_t* v, int64_t* lc
   if (!m || !nedges) return set_error(FAMSA_LCS_EINVAL, "NULL argument");
   FAMSA_HIP(hipSetDevice(m->device));
   FAMSA_HIP(hipDeviceSynchronize());
-  const uint32_t n = m->nf;
+  MstDev::Ctl c;
+  FAMSA_HIP(hipMemcpy(&c, m->ctl.p, sizeof c, hipMemcpyDeviceToHost));
+  const uint32_t n = c.nf;
   std::vector<uint32_t> hu(n), hv(n), hl(m->k);
   std::vector<int32_t> hL(n);
   if (n) {
@@ -425,6 +568,18 @@ int famsa_mst_result(const famsa_mst_t* m, uint32_t* u, uint32_t* v, int64_t* lc
     if (indel2) indel2[e] = d * d;
   }
   *nedges = n;
+  return 0;
+}
+
+int famsa_mst_get_stats(const famsa_mst_t* m, uint64_t* tiles, uint64_t* rounds) {
+  clear_error();
+  if (!m) return set_error(FAMSA_LCS_EINVAL, "mst is NULL");
+  FAMSA_HIP(hipSetDevice(m->device));
+  FAMSA_HIP(hipDeviceSynchronize());
+  MstDev::Ctl c;
+  FAMSA_HIP(hipMemcpy(&c, m->ctl.p, sizeof c, hipMemcpyDeviceToHost));
+  if (tiles) *tiles = m->tiles;
+  if (rounds) *rounds = c.rounds;
   return 0;
 }
 

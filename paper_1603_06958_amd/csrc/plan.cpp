@@ -47,10 +47,8 @@ struct famsa_lcs_plan_s {
   DevMem d_out[2];
   PinMem h_out[2];
   uint64_t step_cap = 0;  // values per step buffer
-  hipStream_t cs[2] = {nullptr, nullptr};
-  static constexpr int kCopyStreams = 4;  // device-to-host copies split across DMA engines
-  hipStream_t xs[kCopyStreams] = {};
-  hipEvent_t ev_xdone[2][kCopyStreams] = {};
+  hipStream_t cs[2] = {nullptr, nullptr};  // the device's shared compute streams
+  hipStream_t xs = nullptr;                 // and its copy stream
   hipEvent_t ev_comp[2] = {}, ev_copy[2] = {}, ev_s0[2] = {}, ev_s1[2] = {}, ev_user = nullptr;
   hipEvent_t ev_k[2][10] = {};
   std::map<uint64_t, hipGraphExec_t> graphs[2];  // per compute stream, per launch signature
@@ -81,6 +79,7 @@ struct famsa_lcs_plan_s {
   int dump(const char* path) const;
   int setup_device();
   int capture_graphs();
+  int capture_on(hipStream_t cap, const DeviceBatch& b, const DeviceWork& w);
   int enqueue_step(uint64_t s, int slot, bool timed);
   int upload_work();
   void drop_graphs() {
@@ -94,11 +93,12 @@ struct famsa_lcs_plan_s {
 };
 
 famsa_lcs_plan_s::~famsa_lcs_plan_s() {
+  // the streams are shared: wait for this plan's own work only
   for (int i = 0; i < 2; ++i) {
-    if (cs[i]) (void)hipStreamSynchronize(cs[i]);
+    if (ev_comp[i]) (void)hipEventSynchronize(ev_comp[i]);
+    if (ev_copy[i]) (void)hipEventSynchronize(ev_copy[i]);
   }
-  for (hipStream_t x : xs)
-    if (x) (void)hipStreamSynchronize(x);
+  if (cs[0]) (void)hipStreamSynchronize(cs[0]);  // set-up and tuning work
   drop_graphs();
   for (int i = 0; i < 2; ++i) {
     if (ev_comp[i]) (void)hipEventDestroy(ev_comp[i]);
@@ -107,14 +107,8 @@ famsa_lcs_plan_s::~famsa_lcs_plan_s() {
     if (ev_s1[i]) (void)hipEventDestroy(ev_s1[i]);
     for (int j = 0; j < 10; ++j)
       if (ev_k[i][j]) (void)hipEventDestroy(ev_k[i][j]);
-    if (cs[i]) (void)hipStreamDestroy(cs[i]);
   }
   if (ev_user) (void)hipEventDestroy(ev_user);
-  for (int i = 0; i < 2; ++i)
-    for (hipEvent_t e : ev_xdone[i])
-      if (e) (void)hipEventDestroy(e);
-  for (hipStream_t x : xs)
-    if (x) (void)hipStreamDestroy(x);
 }
 
 int famsa_lcs_plan_s::build_tiles_and_steps() {
@@ -214,11 +208,10 @@ int famsa_lcs_plan_s::dump(const char* path) const {
 }
 
 int famsa_lcs_plan_s::setup_device() {
-  FAMSA_HIP(hipStreamCreateWithFlags(&cs[0], hipStreamNonBlocking));
-  FAMSA_HIP(hipStreamCreateWithFlags(&cs[1], hipStreamNonBlocking));
-  for (hipStream_t& x : xs) FAMSA_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-  for (int i = 0; i < 2; ++i)
-    for (hipEvent_t& e : ev_xdone[i]) FAMSA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  int rc;
+  if ((rc = lib_stream(opt.device, 0, &cs[0])) || (rc = lib_stream(opt.device, 1, &cs[1])) ||
+      (rc = lib_stream(opt.device, kCopyStream, &xs)))
+    return rc;
   for (int i = 0; i < 2; ++i) {
     FAMSA_HIP(hipEventCreateWithFlags(&ev_comp[i], hipEventDisableTiming));
     FAMSA_HIP(hipEventCreateWithFlags(&ev_copy[i], hipEventDisableTiming));
@@ -235,14 +228,23 @@ int famsa_lcs_plan_s::setup_device() {
 int famsa_lcs_plan_s::capture_graphs() {
   const DeviceBatch b = batch.view();
   const DeviceWork w = work();
+  // capture on a stream of its own: the shared streams may carry other work
+  hipStream_t cap = nullptr;
+  FAMSA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  int rc = capture_on(cap, b, w);
+  (void)hipStreamDestroy(cap);
+  return rc;
+}
+
+int famsa_lcs_plan_s::capture_on(hipStream_t cap, const DeviceBatch& b, const DeviceWork& w) {
   for (int slot = 0; slot < 2; ++slot) {
     for (const StepSig& sg : wl.sigs) {
       if (graphs[slot].count(sg.key())) continue;
       hipGraph_t g = nullptr;
-      FAMSA_HIP(hipStreamBeginCapture(cs[slot], hipStreamCaptureModeThreadLocal));
+      FAMSA_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
       int rc = exec.enqueue(sg, b, w, ctl(slot), d_out[slot].as<int32_t>(), d_plainwork[slot].as<uint64_t>(),
-                            d_carry[slot].as<uint32_t>(), cs[slot], nullptr);
-      hipError_t e = hipStreamEndCapture(cs[slot], &g);  // a graph can be launched on any stream
+                            d_carry[slot].as<uint32_t>(), cap, nullptr);
+      hipError_t e = hipStreamEndCapture(cap, &g);  // a graph can be launched on any stream
       if (rc) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -414,31 +416,20 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
     int rc = enqueue_step(s, slot, timed);
     if (rc) return rc;
     if (!dev_tiles) {
-      // split the step's values over the copy streams; the last one joins them
-      const uint64_t bytes = steps[s].values * sizeof(int32_t);
-      const uint64_t part = (bytes / kCopyStreams + 4095) & ~4095ull;
-      int used = 0;
-      for (int x = 0; x < kCopyStreams; ++x) {
-        const uint64_t off = part * x;
-        if (off >= bytes) break;
-        const uint64_t n = std::min(part, bytes - off);
-        FAMSA_HIP(hipStreamWaitEvent(xs[x], ev_comp[slot], 0));
-        FAMSA_HIP(hipMemcpyAsync(static_cast<char*>(h_out[slot].p) + off, static_cast<char*>(d_out[slot].p) + off, n,
-                                 hipMemcpyDeviceToHost, xs[x]));
-        FAMSA_HIP(hipEventRecord(ev_xdone[slot][x], xs[x]));
-        ++used;
-      }
-      if (used == 0) FAMSA_HIP(hipStreamWaitEvent(xs[0], ev_comp[slot], 0));
-      for (int x = 1; x < used; ++x) FAMSA_HIP(hipStreamWaitEvent(xs[0], ev_xdone[slot][x], 0));
-      FAMSA_HIP(hipEventRecord(ev_copy[slot], xs[0]));
+      FAMSA_HIP(hipStreamWaitEvent(xs, ev_comp[slot], 0));
+      FAMSA_HIP(hipMemcpyAsync(h_out[slot].p, d_out[slot].p, steps[s].values * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               xs));
+      FAMSA_HIP(hipEventRecord(ev_copy[slot], xs));
     } else {
       FAMSA_HIP(hipEventRecord(ev_copy[slot], cstream(slot)));
     }
     return 0;
   };
   auto drain = [&]() {
-    for (int i = 0; i < 2; ++i) (void)hipStreamSynchronize(cs[i]);
-    for (hipStream_t x : xs) (void)hipStreamSynchronize(x);
+    for (int i = 0; i < 2; ++i) {
+      (void)hipEventSynchronize(ev_comp[i]);
+      (void)hipEventSynchronize(ev_copy[i]);
+    }
   };
   int rc = 0;
   for (uint64_t s = s0; s < ns && s < s0 + nslots && !rc; ++s) rc = issue(s);

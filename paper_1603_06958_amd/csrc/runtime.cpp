@@ -7,6 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 namespace famsa {
@@ -392,6 +395,29 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
   sig.plain = plain_pairs ? 1 : 0;
   wl.ranges.push_back(r);
   wl.sigs.push_back(sig);
+}
+
+int lib_stream(int device, int i, hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, std::array<hipStream_t, kLibStreams>> pool;
+  if (i < 0 || i >= kLibStreams) return set_error(FAMSA_LCS_EINVAL, "stream index %d", i);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pool.find(device);
+  if (it == pool.end()) it = pool.emplace(device, std::array<hipStream_t, kLibStreams>{}).first;
+  hipStream_t& st = it->second[i];
+  if (!st) {
+    int cur = 0;
+    FAMSA_HIP(hipGetDevice(&cur));
+    FAMSA_HIP(hipSetDevice(device));
+    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    FAMSA_HIP(hipSetDevice(cur));
+    if (e != hipSuccess) {
+      st = nullptr;
+      return set_error(FAMSA_LCS_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+  }
+  *out = st;
+  return 0;
 }
 
 int gpu_info(int device, GpuInfo* gi) {

@@ -162,6 +162,16 @@ struct GpuInfo {
 };
 int gpu_info(int device, GpuInfo* gi);
 
+// The streams the library runs on, per device: two compute streams and one
+// copy stream, made on first use and kept until the process ends.  HIP backs
+// a process's streams with a few hardware queues (four by default) and
+// streams beyond those share a queue, running one after the other; streams
+// made per plan would therefore lose their overlap as plans come and go.
+// Every plan and server on a device shares these three.
+constexpr int kLibStreams = 3;
+constexpr int kCopyStream = 2;
+int lib_stream(int device, int i, hipStream_t* out);
+
 // Class of a group with W dwords per lane (3 = segmented long rows).
 int class_of(uint32_t W, uint32_t sigma);
 

@@ -89,7 +89,7 @@ struct famsa_lcs_server_s {
   std::deque<Job*> queue;
   std::vector<Job*> active;
   uint32_t next_id = 0;
-  hipStream_t cs = nullptr, xs = nullptr;
+  hipStream_t cs = nullptr, xs = nullptr;  // the device's shared compute and copy streams
   Slot slot[2];
   uint64_t step_no = 0;
   // host staging kept alive until the step's uploads complete
@@ -103,8 +103,6 @@ struct famsa_lcs_server_s {
     if (xs) (void)hipStreamSynchronize(xs);
     for (auto& sl : slot)
       if (sl.done) (void)hipEventDestroy(sl.done);
-    if (cs) (void)hipStreamDestroy(cs);
-    if (xs) (void)hipStreamDestroy(xs);
   }
   int admit();
   int compose(Slot& sl, Staging& st);
@@ -294,8 +292,7 @@ int famsa_lcs_server_create(const famsa_lcs_options* opt, famsa_lcs_server_t** o
     s->fixed = 2 * s->step_values * 4 + (s->budget / 8);
   }
   if (s->fixed >= s->budget) return set_error(FAMSA_LCS_ENOMEM, "budget %llu too small", (unsigned long long)s->budget);
-  FAMSA_HIP(hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking));
-  FAMSA_HIP(hipStreamCreateWithFlags(&s->xs, hipStreamNonBlocking));
+  if ((rc = lib_stream(o.device, 0, &s->cs)) || (rc = lib_stream(o.device, kCopyStream, &s->xs))) return rc;
   for (auto& sl : s->slot) {
     FAMSA_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
     if ((rc = sl.d_out.alloc(s->step_values * 4)) || (rc = sl.h_out.alloc(s->step_values * 4))) return rc;

@@ -102,12 +102,13 @@ def test_tree_matches_oracle(seed, k, lo, hi, sigma, R, flags):
     assert (cophenetic_from_tree(k, got) == c_ref).all()
 
 
-def test_heights_match_host_slink_c2_like():
-    b = inputs.c2(k=3000)
-    k = b.nseq
-    u, v, l, d = gpu_tree(b, tile_rows=256, step_values=200_000)
+@pytest.mark.parametrize("k,R", [(3000, 256), (9000, 700)])
+def test_heights_match_host_slink_c2_like(k, R):
+    # k = 9000 spans three 4096-column chunks of the row pass
+    b = inputs.c2(k=k)
+    u, v, l, d = gpu_tree(b, tile_rows=R, step_values=2_000_000)
     s = B.SLink(b.lengths())
-    with B.Plan.from_batch(b, tile_rows=256, flags=B.DESCENDING) as p:
+    with B.Plan.from_batch(b, tile_rows=R, flags=B.DESCENDING) as p:
         p.run_native(B.SLink.consume_fn(), s.handle)
     pi, num, den = s.result()
     slink_h = sorted(sim(n, q) for n, q in zip(num, den) if not (n == -1 and q == 0))
