@@ -1,18 +1,27 @@
 """Benchmark of the all-pairs LCS similarity stage on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c1]
-                    [--no-c3] [--no-serve] [--no-cpu]
+                    [--no-c3] [--no-serve] [--no-cpu] [--no-extra]
 
 One step = one full pass of the stage over the workload: every row tile of
-the family computed on the GPU (masks resident in HBM; the plan is built
-before the timed region) and copied to pinned host memory, where the tile
-callback receives it.  `value` is GCUPS = sum over pairs of |A||B| divided
-by the wall time of a step.  Also reported, in the same JSON line:
+the family computed on the GPU (masks resident in HBM; the plan is built and
+tuned before the timed region) and copied to pinned host memory, where the
+tile callback receives it.  `value` is GCUPS = sum over pairs of |A||B|
+divided by the wall time of a step.  The timed steps run on one compute
+stream, so no two launches overlap and each launch's event-timed duration is
+the kernel's own.  Also reported, in the same JSON line:
 
 * roofline: the dominant LCS kernel's integer-ALU throughput (3 VALU ops
   per 32 cells: AND, ADD-with-carry, the three-input OR/AND-NOT) against
-  gfx950's 256 CUs x 64 lanes x 2.4 GHz, from HIP events around each launch
-  on its own stream during the timed steps;
+  gfx950's 256 CUs x 128 lanes x 2.4 GHz, from HIP events around each launch
+  on its stream during the timed steps; `traffic` is that kernel's HBM bytes
+  per launch from the committed rocprofv3 counter summary when it was taken
+  from the current kernel source and this configuration, else null;
+* two_streams: the same pass with consecutive steps on two compute streams
+  (the library default), where one step's tail overlaps the next step;
+* gpu_single_linkage: the pass with device tiles feeding the GPU exact
+  single-linkage consumer (maximum spanning tree of the similarities);
+* host_slink: the host SLINK consumer's update rate on c2;
 * cpu_baseline: the CPU oracle (plain DP) on a bounded sample of the same
   workload's pairs, on the host's cores;
 * c3: batched (persistent, graph-replayed) vs plain per-family launches;
@@ -39,6 +48,9 @@ METRIC = "GCUPS for all-pairs bit-parallel LCS (k=100k), batched vs plain; serve
 # the ceiling.
 PEAK_INT_OPS = 256 * 128 * 2.4e9
 OPS_PER_CELL = 3.0 / 32.0             # AND + ADDC + BITOP3 per 32-cell dword-step
+STEP_VALUES = 1 << 28                 # int32 results per launch step (1 GiB per buffer)
+TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "lcs_fast_c4_hbm_traffic.txt")
+KERNEL_SOURCE = os.path.join(HERE, "paper_1603_06958_amd", "csrc", "lcs_kernels.hip")
 
 
 def _oracle_worker(args):
@@ -86,10 +98,10 @@ def cpu_baseline(b, seconds_target=12.0, seed=7):
                       f"{cores} single-threaded processes, {wall:.1f} s wall"}
 
 
-def run_main(b, steps, warmup, tile_rows=1024, tune=True):
+def run_main(b, steps, warmup, flags, tile_rows=1024, tune=True):
     from paper_1603_06958_amd import binding as B
     import torch
-    p = B.Plan.from_batch(b, tile_rows=tile_rows)
+    p = B.Plan.from_batch(b, tile_rows=tile_rows, flags=flags, step_values=STEP_VALUES)
     if tune:
         t0 = time.perf_counter()
         p.autotune(os.environ.get("FAMSA_LCS_TUNE_CACHE") or None)
@@ -115,6 +127,61 @@ def run_main(b, steps, warmup, tile_rows=1024, tune=True):
         kstats.append(p.stats())
     p.close()
     return info, times, kstats, sink[0]
+
+
+def run_gpu_single_linkage(b, passes=2):
+    """Device tiles into the GPU exact single-linkage consumer; best of `passes`."""
+    from paper_1603_06958_amd import binding as B
+    p = B.Plan.from_batch(b, flags=B.DEVICE_TILES, step_values=STEP_VALUES)
+    p.autotune(os.environ.get("FAMSA_LCS_TUNE_CACHE") or None)
+    best, edges, rounds = None, 0, 0
+    for _ in range(passes):
+        m = B.Mst(b.lengths())
+        t0 = time.perf_counter()
+        p.run_native(B.Mst.consume_fn(), m.handle)
+        u = m.result()[0]
+        dt = time.perf_counter() - t0
+        edges, rounds = len(u), m.stats()[1]
+        m.close()
+        best = dt if best is None else min(best, dt)
+    p.close()
+    return {"s": round(best, 4), "gcups": round(b.cells() / best / 1e9, 1), "tree_edges": edges,
+            "boruvka_rounds": rounds, "delivery": "device tiles on two compute streams"}
+
+
+def run_host_slink():
+    """Host SLINK (exact rational similarities) over all of c2's tiles."""
+    from paper_1603_06958_amd import binding as B, inputs
+    b = inputs.c2()
+    s = B.SLink(b.lengths())
+    p = B.Plan.from_batch(b, flags=B.DESCENDING)
+    t0 = time.perf_counter()
+    p.run_native(B.SLink.consume_fn(), s.handle)
+    dt = time.perf_counter() - t0
+    p.close()
+    s.close()
+    return {"workload": "c2: one tree-evolved family, k=10000", "s": round(dt, 3),
+            "pair_updates_per_s": round(b.pairs() / dt, 1), "threads": 1}
+
+
+def traffic_per_launch(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken from the current kernel source in the bench configuration."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None, "no counter summary"
+    if f"sha256[:16] = {sha}" not in text:
+        return None, "kernel changed since the counters were taken"
+    if f"step_values {STEP_VALUES}, one compute stream" not in text:
+        return None, "counters taken in another configuration"
+    for line in text.splitlines():
+        f = line.split()
+        if f and f[0] == kernel and len(f) >= 6:
+            return int(round((float(f[4]) + float(f[5])) * 1e6)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+    return None, "kernel not in the counter summary"
 
 
 def run_c3(steps=1):
@@ -160,6 +227,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the two-stream, GPU single-linkage and host SLINK measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for scaling HBM byte counters)")
     a = ap.parse_args()
@@ -183,7 +252,8 @@ def main():
     b = inputs.WORKLOADS[a.workload]()
     print(f"[bench] generated {a.workload} in {time.time() - t0:.1f}s: {inputs.stats(b)}", file=sys.stderr,
           flush=True)
-    info, times, kst, count = run_main(b, a.steps, a.warmup)
+    from paper_1603_06958_amd import binding as B
+    info, times, kst, count = run_main(b, a.steps, a.warmup, flags=B.ONE_STREAM | B.NO_GRAPH)
     cells = info.cells
     ms = 1e3 * float(np.mean(times))
     value = cells / (ms / 1e3) / 1e9
@@ -192,6 +262,8 @@ def main():
     kms = float(np.mean([s.kernel_ms[cls] / max(1, s.launches[cls]) for s in kst]))
     per_launch_cells = kst[-1].cells[cls] / max(1, kst[-1].launches[cls])
     achieved = per_launch_cells * OPS_PER_CELL / (kms / 1e3)
+    kname = f"lcs_fast_kernel<{cls},20>"
+    traffic, traffic_src = traffic_per_launch(kname)
     print(f"[bench] steps {[round(t, 3) for t in times]} s; kernel classes ms "
           f"{[round(x, 1) for x in kst[-1].kernel_ms]} launches {list(kst[-1].launches)} "
           f"step_ms {kst[-1].step_ms:.1f}", file=sys.stderr, flush=True)
@@ -204,18 +276,31 @@ def main():
                                 "c2": "c2: one tree-evolved family, k=10000, root 300, seed 1",
                                 "c1": "c1: k=100 i.i.d., lengths U[50,300], seed 0"}[a.workload],
                    "k": b.nseq, "pairs": info.pairs, "cells": cells, "tile_rows": 1024,
+                   "step_values": STEP_VALUES, "streams": "one compute stream, one copy stream",
                    "delivery": "host pinned memory, callback per tile"},
         "pairs_per_s": round(info.pairs / (ms / 1e3), 1),
         "whole_job_alu_frac": round(cells * OPS_PER_CELL / (ms / 1e3) / PEAK_INT_OPS, 4),
         "device_gcups": round(cells / (kst[-1].step_ms / 1e3) / 1e9, 1),
         "peak_hbm_bytes": int(info.device_bytes),
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_INT_OPS / 1e12, 3),
-                     "unit": "Tops/s (int32 VALU)", "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": None,
-                     "kernel": f"lcs_fast_kernel<{cls}>", "avg_launch_ms": round(kms, 3),
+                     "unit": "Tops/s (int32 VALU)", "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (read + write)", "traffic_source": traffic_src,
+                     "kernel": kname, "avg_launch_ms": round(kms, 3),
                      "cells_per_launch": int(per_launch_cells),
                      "ops_per_cell": "3/32 (AND, ADDC, BITOP3 per 32-cell dword)"},
         "launch": {"cols_per_item": int(info.cols_per_item), "waves_per_group": list(info.waves_per_group)[:3]},
     }
+    if not a.no_extra:
+        _, t2, _, _ = run_main(b, 2, 1, flags=0, tune=True)
+        res["two_streams"] = {"value": round(cells / min(t2) / 1e9, 1), "unit": "GCUPS",
+                              "ms_per_step": round(1e3 * min(t2), 2),
+                              "note": "same pass, consecutive steps on two compute streams (library default)"}
+        print(f"[bench] two_streams {res['two_streams']}", file=sys.stderr, flush=True)
+        if a.workload == "c4":
+            res["gpu_single_linkage"] = run_gpu_single_linkage(b)
+            print(f"[bench] gpu_single_linkage {res['gpu_single_linkage']}", file=sys.stderr, flush=True)
+        res["host_slink"] = run_host_slink()
+        print(f"[bench] host_slink {res['host_slink']}", file=sys.stderr, flush=True)
     if not a.no_c3:
         res["c3"] = run_c3()
         print(f"[bench] c3 {res['c3']}", file=sys.stderr, flush=True)

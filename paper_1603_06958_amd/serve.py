@@ -137,12 +137,22 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
             "peak_device_bytes": mem[1], "latencies_ms": lat, "job_ids": ids}
 
 
+# Serving steps are kept small so that a new job waits for little work ahead of
+# it: 2^24 values per step (64 MiB per buffer) and 512-row tiles, which hold
+# families of up to ~32,000 sequences.  On the c5 mix this trades ~3% of
+# throughput for a ~4x lower median latency than 2^27-value steps.
+SERVE_STEP_VALUES = 1 << 24
+SERVE_TILE_ROWS = 512
+
+
 def run_c5_bench(njobs: int = 40, rate: float = C5_RATE_PER_S, seed: int = 4) -> Dict:
     jobs = inputs.c5(seed=seed, njobs=njobs, rate_per_s=rate)
-    r = run_jobs(jobs)
+    r = run_jobs(jobs, step_values=SERVE_STEP_VALUES, tile_rows=SERVE_TILE_ROWS)
     r.pop("latencies_ms")
     r.pop("job_ids")
     r["workload"] = (f"c5: {njobs} jobs, Poisson arrivals at {rate} jobs/s, each a tree-evolved family with k "
                      f"log-uniform [100,20000] and root length log-uniform [50,1500], seed {seed}")
     r["arrival_rate_per_s"] = rate
+    r["step_values"] = SERVE_STEP_VALUES
+    r["tile_rows"] = SERVE_TILE_ROWS
     return r
