@@ -55,9 +55,8 @@ typedef enum famsa_lcs_status {
 #define FAMSA_LCS_DESCENDING   0x2u  /* deliver each family's row tiles from the last to the first */
 #define FAMSA_LCS_DEVICE_TILES 0x4u  /* deliver device pointers (no copy to host); valid during the callback,
                                         whose GPU work must be ordered on famsa_lcs_tile.stream */
-#define FAMSA_LCS_NO_GRAPH     0x8u  /* launch kernels directly instead of replaying captured hipGraphs (graphs
-                                        are used for plans of one launch step or with FAMSA_LCS_ONE_STREAM;
-                                        plans of several steps overlap two streams with direct launches) */
+#define FAMSA_LCS_NO_GRAPH     0x8u  /* launch kernels directly (timed per kernel class) instead of replaying
+                                        one captured hipGraph per launch step */
 #define FAMSA_LCS_NO_AUTOTUNE  0x10u /* use the built-in launch parameters; ignore the tuning cache */
 #define FAMSA_LCS_ONE_STREAM   0x20u /* run every launch step on one compute stream (by default consecutive steps
                                         overlap on two); per-kernel timings then exclude the other stream */

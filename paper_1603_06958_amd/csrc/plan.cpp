@@ -65,13 +65,9 @@ struct famsa_lcs_plan_s {
   bool plain() const { return opt.flags & FAMSA_LCS_PLAIN; }
   // compute stream of a buffer slot: both slots share stream 0 under ONE_STREAM
   hipStream_t cstream(int slot) const { return (opt.flags & FAMSA_LCS_ONE_STREAM) ? cs[0] : cs[slot]; }
-  // Graph replays of two streams do not overlap on this runtime, while direct
-  // launches do; so graphs are used where there is nothing to overlap: plans
-  // of one launch step (the batched form), or one compute stream.
-  bool use_graph() const {
-    if (opt.flags & (FAMSA_LCS_NO_GRAPH | FAMSA_LCS_PLAIN)) return false;
-    return steps.size() <= 1 || (opt.flags & FAMSA_LCS_ONE_STREAM);
-  }
+  // Steps replay captured graphs unless FAMSA_LCS_NO_GRAPH asks for direct
+  // launches (which are timed per kernel class with events).
+  bool use_graph() const { return !(opt.flags & (FAMSA_LCS_NO_GRAPH | FAMSA_LCS_PLAIN)); }
   ~famsa_lcs_plan_s();
   int build_tiles_and_steps();
   int build_work();
