@@ -60,6 +60,15 @@ typedef enum famsa_lcs_status {
 #define FAMSA_LCS_NO_AUTOTUNE  0x10u /* use the built-in launch parameters; ignore the tuning cache */
 #define FAMSA_LCS_ONE_STREAM   0x20u /* run every launch step on one compute stream (by default consecutive steps
                                         overlap on two); per-kernel timings then exclude the other stream */
+#define FAMSA_LCS_OUT_INDEL    0x40u /* tiles hold indel = |A| + |B| - 2 LCS (int32) instead of LCS */
+#define FAMSA_LCS_OUT_SIM      0x80u /* tiles hold the similarity LCS / indel^2 as float32 (the float rounding
+                                        of the correctly rounded double; +infinity when indel = 0) instead of
+                                        LCS (Methods, "Pairwise similarities calculation"); excludes OUT_INDEL */
+
+/* What a tile's values are (famsa_lcs_tile.values). */
+#define FAMSA_LCS_VALUES_LCS   0u
+#define FAMSA_LCS_VALUES_INDEL 1u
+#define FAMSA_LCS_VALUES_SIM   2u
 
 typedef struct famsa_lcs_options {
   uint32_t struct_size;    /* sizeof(famsa_lcs_options) as the caller compiled it */
@@ -105,9 +114,11 @@ typedef struct famsa_lcs_tile {
   uint32_t family;       /* family id (serving: job id) */
   uint32_t k;            /* family size */
   uint32_t row_begin, row_end;
-  const int32_t* lcs;    /* host memory, or device memory under FAMSA_LCS_DEVICE_TILES */
+  const int32_t* lcs;    /* host memory, or device memory under FAMSA_LCS_DEVICE_TILES; int32 LCS values,
+                            or indel / float32 similarity bits as `values` says */
   uint64_t count;
   void* stream;          /* hipStream_t the tile was produced on */
+  uint32_t values;       /* FAMSA_LCS_VALUES_*: LCS unless the plan asked for OUT_INDEL or OUT_SIM */
 } famsa_lcs_tile;
 
 /* Tile consumer; return 0 to continue, nonzero to cancel. */
@@ -198,6 +209,12 @@ int famsa_slink_consume(void* slink, const famsa_lcs_tile* tile);
  * num >= 0 is +infinity (identical sequences), and the root has num -1,
  * den 0 (never joins).  NULL outputs are skipped.  EINVAL before all rows. */
 int famsa_slink_result(const famsa_slink_t* s, uint32_t* pi, int64_t* lambda_num, int64_t* lambda_den);
+/* The guide tree from the pointer representation: every point i but the
+ * root joins the cluster of pi[i] at similarity lambda[i]; as
+ * famsa_guide_tree over the pairs (i, pi[i]).  Arrays of k-1; EINVAL before
+ * all rows. */
+int famsa_slink_guide_tree(const famsa_slink_t* s, uint32_t* left, uint32_t* right, int64_t* lambda_num,
+                           int64_t* lambda_den, uint32_t* nmerges);
 /* Rows inserted so far. */
 uint32_t famsa_slink_rows_done(const famsa_slink_t* s);
 void famsa_slink_destroy(famsa_slink_t* s);
@@ -228,9 +245,31 @@ int famsa_mst_consume(void* mst, const famsa_lcs_tile* tile);
  * Arrays hold k entries; NULL ones are skipped. */
 int famsa_mst_result(const famsa_mst_t* mst, uint32_t* u, uint32_t* v, int64_t* lcs, int64_t* indel2,
                      uint32_t* nedges);
+/* The guide tree of the forest (famsa_guide_tree below), arrays of k-1. */
+int famsa_mst_guide_tree(const famsa_mst_t* mst, uint32_t* left, uint32_t* right, int64_t* lcs, int64_t* indel2,
+                         uint32_t* nmerges);
 /* Tiles merged so far and the Boruvka rounds that joined components. */
 int famsa_mst_get_stats(const famsa_mst_t* mst, uint64_t* tiles, uint64_t* rounds);
 void famsa_mst_destroy(famsa_mst_t* mst);
+
+/* ------------------------------------------------------------------------
+ * Guide tree (Methods, "Determination of the guide tree"; the progressive
+ * stage merges profiles in the tree's bottom-up order).  Host code, no GPU.
+ *
+ * Input: nedges <= k-1 edges (u[e], v[e]) of a spanning forest of the k
+ * sequences (family-local indices, u != v) with similarity num[e] / den[e]
+ * (den 0 = +infinity, e.g. LCS and indel^2).  Output: the single-linkage
+ * merges, most similar first, equal similarities by the edge (min, max)
+ * lexicographically: merge t joins clusters left[t] (holding the edge's
+ * smaller end) and right[t] into cluster k + t; clusters 0..k-1 are the
+ * sequences.  merge_num/merge_den receive each merge's similarity;
+ * *nmerges = nedges.  Output arrays hold nedges entries, NULL ones are
+ * skipped.  EINVAL if an edge is out of range, has a negative similarity, or
+ * closes a cycle.
+ * ------------------------------------------------------------------------ */
+int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
+                     uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* merge_num, int64_t* merge_den,
+                     uint32_t* nmerges);
 
 /* ------------------------------------------------------------------------
  * Serving: similarity jobs (each one family) are admitted while their device

@@ -198,3 +198,39 @@ def single_linkage(lcs_mat: np.ndarray, lengths: Sequence[int]) -> Tuple[List, n
         members[ri] += members.pop(rj)
         heights.append(s)
     return heights, coph
+
+
+def guide_tree(lcs_mat: np.ndarray, lengths: Sequence[int]) -> List[Tuple[int, int, object]]:
+    """The single-linkage guide tree as a merge list (Methods, "Determination
+    of the guide tree"), by Kruskal's algorithm over all pairs.
+
+    Pairs are taken most similar first; equal similarities by the pair
+    (i, j), i < j, in lexicographic order.  A pair whose ends lie in
+    different clusters merges them: merge t joins the cluster holding i
+    (left) and the cluster holding j (right) into cluster k + t; clusters
+    0..k-1 are the sequences.  Returns [(left, right, similarity)].
+    """
+    k = lcs_mat.shape[0]
+    edges = []
+    for i in range(k):
+        for j in range(i + 1, k):
+            edges.append((similarity(int(lcs_mat[i, j]), int(lengths[i]), int(lengths[j])), i, j))
+    edges.sort(key=lambda e: (-1, 0, e[1], e[2]) if e[0] == INF else (0, -e[0], e[1], e[2]))
+    parent = list(range(k))
+    cluster = list(range(k))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    merges = []
+    for s, i, j in edges:
+        ri, rj = find(i), find(j)
+        if ri == rj:
+            continue
+        merges.append((cluster[ri], cluster[rj], s))
+        parent[ri] = rj
+        cluster[rj] = k + len(merges) - 1
+    return merges

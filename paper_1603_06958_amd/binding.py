@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libfamsa_lcs.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5
 PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE, ONE_STREAM = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+OUT_INDEL, OUT_SIM = 0x40, 0x80
+VALUES_LCS, VALUES_INDEL, VALUES_SIM = 0, 1, 2
 MAX_LEN = 65535
 
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECANCELED: "ECANCELED", EBUSY: "EBUSY"}
@@ -39,7 +41,8 @@ class Options(ctypes.Structure):
 class Tile(ctypes.Structure):
     _fields_ = [("tile_index", ctypes.c_uint64), ("family", ctypes.c_uint32), ("k", ctypes.c_uint32),
                 ("row_begin", ctypes.c_uint32), ("row_end", ctypes.c_uint32),
-                ("lcs", ctypes.POINTER(ctypes.c_int32)), ("count", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
+                ("lcs", ctypes.POINTER(ctypes.c_int32)), ("count", ctypes.c_uint64), ("stream", ctypes.c_void_p),
+                ("values", ctypes.c_uint32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -107,6 +110,13 @@ def lib():
         L.famsa_mst_get_stats.restype = ctypes.c_int
         L.famsa_mst_destroy.argtypes = [vp]
         L.famsa_mst_destroy.restype = None
+        L.famsa_mst_guide_tree.argtypes = [vp, u32p, u32p, i64p, i64p, u32p]
+        L.famsa_mst_guide_tree.restype = ctypes.c_int
+        L.famsa_slink_guide_tree.argtypes = [vp, u32p, u32p, i64p, i64p, u32p]
+        L.famsa_slink_guide_tree.restype = ctypes.c_int
+        L.famsa_guide_tree.argtypes = [ctypes.c_uint32, u32p, u32p, i64p, i64p, ctypes.c_uint32, u32p, u32p, i64p,
+                                       i64p, u32p]
+        L.famsa_guide_tree.restype = ctypes.c_int
         L.famsa_lcs_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.famsa_lcs_server_create.restype = ctypes.c_int
         L.famsa_lcs_server_submit.argtypes = [vp, u8p, u64p, ctypes.c_uint32, u32p]
@@ -233,12 +243,12 @@ class Plan:
         return check(lib().famsa_lcs_tiles(self.handle, first_tile, fn_ptr, user))
 
     def collect(self, first_tile: int = 0) -> Dict[Tuple[int, int, int], np.ndarray]:
-        """All host tiles as {(family, row_begin, row_end): int32 array copy}."""
+        """All host tiles as {(family, row_begin, row_end): array copy} (int32,
+        or float32 similarities under OUT_SIM)."""
         out = {}
 
         def fn(t: Tile):
-            arr = np.ctypeslib.as_array(t.lcs, shape=(t.count,)).copy() if t.count else np.zeros(0, np.int32)
-            out[(t.family, t.row_begin, t.row_end)] = arr
+            out[(t.family, t.row_begin, t.row_end)] = tile_array(t).copy()
             return 0
 
         self.run(fn, first_tile)
@@ -249,10 +259,46 @@ class Plan:
 
 
 def tile_array(t: Tile) -> np.ndarray:
-    """View of a host tile's values (valid during the callback only)."""
+    """View of a host tile's values (valid during the callback only): int32
+    LCS or indel values, or float32 similarities under OUT_SIM."""
+    dt = np.float32 if t.values == VALUES_SIM else np.int32
     if t.count == 0:
-        return np.zeros(0, np.int32)
-    return np.ctypeslib.as_array(t.lcs, shape=(t.count,))
+        return np.zeros(0, dt)
+    a = np.ctypeslib.as_array(t.lcs, shape=(t.count,))
+    return a.view(np.float32) if dt is np.float32 else a
+
+
+def _merges(k, call):
+    n = max(k - 1, 1)
+    left, right = np.zeros(n, np.uint32), np.zeros(n, np.uint32)
+    num, den = np.zeros(n, np.int64), np.zeros(n, np.int64)
+    nm = ctypes.c_uint32()
+    check(call(_ptr(left, ctypes.c_uint32), _ptr(right, ctypes.c_uint32), _ptr(num, ctypes.c_int64),
+               _ptr(den, ctypes.c_int64), ctypes.byref(nm)))
+    m = int(nm.value)
+    return left[:m], right[:m], num[:m], den[:m]
+
+
+def guide_tree(k: int, u, v, num, den):
+    """famsa_guide_tree: single-linkage merges of a spanning forest's edges."""
+    u, v = np.ascontiguousarray(u, np.uint32), np.ascontiguousarray(v, np.uint32)
+    num, den = np.ascontiguousarray(num, np.int64), np.ascontiguousarray(den, np.int64)
+    ne = u.size
+    return _merges(k, lambda l, r, a, b, nm: lib().famsa_guide_tree(
+        k, _ptr(u, ctypes.c_uint32) if ne else None, _ptr(v, ctypes.c_uint32) if ne else None,
+        _ptr(num, ctypes.c_int64) if ne else None, _ptr(den, ctypes.c_int64) if ne else None, ne, l, r, a, b, nm))
+
+
+def newick(left, right, k: int, names=None) -> str:
+    """The merge list as a Newick string (leaves named by index or `names`)."""
+    label = [str(i) if names is None else str(names[i]) for i in range(k)]
+    top = set(range(k))
+    for t, (l, r) in enumerate(zip(left, right)):
+        label.append(f"({label[int(l)]},{label[int(r)]})")
+        top -= {int(l), int(r)}
+        top.add(k + t)
+    roots = sorted(top)
+    return (label[roots[0]] if len(roots) == 1 else "(" + ",".join(label[c] for c in roots) + ")") + ";"
 
 
 class SLink:
@@ -284,6 +330,10 @@ class SLink:
         check(lib().famsa_slink_result(self.handle, _ptr(pi, ctypes.c_uint32), _ptr(num, ctypes.c_int64),
                                        _ptr(den, ctypes.c_int64)))
         return pi, num, den
+
+    def guide_tree(self):
+        """(left, right, num, den) of the k-1 merges (famsa_slink_guide_tree)."""
+        return _merges(self.k, lambda *a: lib().famsa_slink_guide_tree(self.handle, *a))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -328,6 +378,10 @@ class Mst:
         t, r = ctypes.c_uint64(), ctypes.c_uint64()
         check(lib().famsa_mst_get_stats(self.handle, ctypes.byref(t), ctypes.byref(r)))
         return int(t.value), int(r.value)
+
+    def guide_tree(self):
+        """(left, right, lcs, indel2) of the k-1 merges (famsa_mst_guide_tree)."""
+        return _merges(self.k, lambda *a: lib().famsa_mst_guide_tree(self.handle, *a))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -1,0 +1,91 @@
+// The single-linkage guide tree as a merge list (paper, Methods,
+// "Determination of the guide tree": FAMSA builds its guide tree by single
+// linkage; the progressive stage merges profiles in the tree's bottom-up
+// order).
+//
+// Input: the k-1 edges of a maximum spanning tree of the similarities (or any
+// edge set whose single-linkage merges they are, such as SLINK's pointer
+// pairs), each with its similarity as the exact rational num/den.  Single
+// linkage joins clusters in the order of decreasing similarity, and at each
+// join the two clusters are the ones holding the edge's ends (Kruskal).  So:
+// sort the edges by similarity, most similar first, equal similarities by the
+// pair (u, v), u < v, lexicographically; then union-find over the sorted
+// edges gives merge t joining clusters left[t] (holding u) and right[t]
+// (holding v) into cluster k + t.  Clusters 0..k-1 are the sequences.
+#include <stdint.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "runtime.h"
+
+namespace famsa {
+
+namespace {
+
+// a strictly more similar than b; den == 0 is +infinity
+inline bool more_similar(int64_t an, int64_t ad, int64_t bn, int64_t bd) {
+  if (ad == 0) return bd != 0;
+  if (bd == 0) return false;
+  return (__int128)an * bd > (__int128)bn * ad;
+}
+
+}  // namespace
+
+int guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
+               uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* mnum, int64_t* mden, uint32_t* nmerges) {
+  if (!nmerges) return set_error(FAMSA_LCS_EINVAL, "nmerges is NULL");
+  *nmerges = 0;
+  if (k == 0) return nedges ? set_error(FAMSA_LCS_EINVAL, "edges given for k = 0") : 0;
+  if (nedges > k - 1) return set_error(FAMSA_LCS_EINVAL, "%u edges for %u sequences (at most k-1)", nedges, k);
+  if (nedges && (!u || !v || !num || !den)) return set_error(FAMSA_LCS_EINVAL, "NULL edge array");
+  std::vector<uint32_t> eu(nedges), ev(nedges), order(nedges);
+  for (uint32_t e = 0; e < nedges; ++e) {
+    if (u[e] >= k || v[e] >= k || u[e] == v[e])
+      return set_error(FAMSA_LCS_EINVAL, "edge %u (%u, %u) is not a pair of distinct sequences < %u", e, u[e], v[e], k);
+    if (den[e] < 0 || (den[e] > 0 && num[e] < 0))
+      return set_error(FAMSA_LCS_EINVAL, "edge %u: similarity %lld/%lld is not >= 0", e, (long long)num[e],
+                       (long long)den[e]);
+    eu[e] = std::min(u[e], v[e]);
+    ev[e] = std::max(u[e], v[e]);
+  }
+  std::iota(order.begin(), order.end(), 0u);
+  std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    if (more_similar(num[a], den[a], num[b], den[b])) return true;
+    if (more_similar(num[b], den[b], num[a], den[a])) return false;
+    return eu[a] != eu[b] ? eu[a] < eu[b] : ev[a] < ev[b];
+  });
+  std::vector<uint32_t> parent(k), cluster(k);
+  std::iota(parent.begin(), parent.end(), 0u);
+  std::iota(cluster.begin(), cluster.end(), 0u);
+  auto find = [&](uint32_t x) {
+    while (parent[x] != x) {
+      parent[x] = parent[parent[x]];
+      x = parent[x];
+    }
+    return x;
+  };
+  for (uint32_t t = 0; t < nedges; ++t) {
+    const uint32_t e = order[t];
+    const uint32_t a = find(eu[e]), b = find(ev[e]);
+    if (a == b) return set_error(FAMSA_LCS_EINVAL, "edge (%u, %u) closes a cycle: the edges are not a forest", eu[e], ev[e]);
+    if (left) left[t] = cluster[a];
+    if (right) right[t] = cluster[b];
+    if (mnum) mnum[t] = num[e];
+    if (mden) mden[t] = den[e];
+    parent[a] = b;
+    cluster[b] = k + t;
+  }
+  *nmerges = nedges;
+  return 0;
+}
+
+}  // namespace famsa
+
+extern "C" int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num,
+                                const int64_t* den, uint32_t nedges, uint32_t* left, uint32_t* right,
+                                int64_t* merge_num, int64_t* merge_den, uint32_t* nmerges) {
+  famsa::clear_error();
+  return famsa::guide_tree(k, u, v, num, den, nedges, left, right, merge_num, merge_den, nmerges);
+}

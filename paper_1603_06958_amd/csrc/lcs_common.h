@@ -28,6 +28,8 @@
 #pragma once
 #include <stdint.h>
 
+#include "../../include/famsa_lcs.h"
+
 namespace famsa {
 
 constexpr int kLanes = 64;        // wavefront size on gfx950
@@ -117,6 +119,7 @@ struct DeviceBatch {
   const uint32_t* len;
   const uint64_t* mask_off;
   const uint32_t* masks;
+  uint32_t values;          // what the tiles hold: FAMSA_LCS_VALUES_LCS, _INDEL or _SIM (float32 bits)
 };
 
 struct DeviceWork {         // descriptor arrays of a plan (all steps) or of one serving step

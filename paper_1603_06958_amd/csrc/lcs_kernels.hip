@@ -116,8 +116,21 @@ __device__ __forceinline__ void lcs_step(uint32_t (&V)[W], const char* __restric
 
 struct LaneCtx {
   uint64_t out_off;
-  uint32_t pos, orig;
+  uint32_t pos, orig, len;
 };
+
+// The value a tile holds for a pair with LCS `lcs` of sequences of lengths
+// la and lb: the LCS, the indel distance la + lb - 2 LCS, or the similarity
+// LCS / indel^2 (Methods, "Pairwise similarities calculation") as the float
+// rounding of the correctly rounded double, +infinity for indel 0.
+__device__ __forceinline__ int32_t tile_value(uint32_t values, uint32_t lcs, uint32_t la, uint32_t lb) {
+  if (values == FAMSA_LCS_VALUES_LCS) return (int32_t)lcs;
+  const int32_t d = (int32_t)(la + lb) - 2 * (int32_t)lcs;
+  if (values == FAMSA_LCS_VALUES_INDEL) return d;
+  const double dd = (double)d * (double)d;  // exact: d <= 131070
+  const float f = d == 0 ? __builtin_inff() : (float)((double)lcs / dd);
+  return __float_as_int(f);
+}
 
 // All columns of one work item for a group with W dwords per lane.  Waves
 // take columns from a shared LDS counter so they stay balanced.  The column
@@ -173,7 +186,7 @@ __device__ __forceinline__ void run_item(const DeviceBatch& bt, const uint32_t* 
     for (int w = 0; w < W; ++w) cnt += __builtin_popcount(~V[w]);
     if (col > lc.pos) {
       const uint64_t o = lc.orig < b ? lc.out_off + (b - lc.orig - 1u) : rb + (lc.orig - b - 1u);
-      out[o] = (int32_t)cnt;
+      out[o] = tile_value(bt.values, cnt, lc.len, n);
     }
   }
 }
@@ -216,7 +229,7 @@ __global__ __launch_bounds__(1024) void lcs_fast_kernel(
     if (it >= end) break;  // same value in every thread
     const ItemDesc item = items[it];
     const GroupDesc g = groups[item.group];
-    LaneCtx lc{0ull, 0xFFFFFFFFu, 0u};  // pos = max: an empty lane never stores
+    LaneCtx lc{0ull, 0xFFFFFFFFu, 0u, 0u};  // pos = max: an empty lane never stores
     uint32_t seq = 0;
     if (lane < g.nrows) {
       const LaneDesc d = lanes[g.lane_first + lane];
@@ -224,6 +237,7 @@ __global__ __launch_bounds__(1024) void lcs_fast_kernel(
       lc.pos = d.pos;
       lc.orig = d.orig;
       seq = d.seq;
+      lc.len = bt.len[seq];
     }
     {  // stage the group's masks in LDS (zero past each row's end and in the padding)
       const uint32_t Q = (g.W + 3u) >> 2;
@@ -420,7 +434,7 @@ __global__ __launch_bounds__(1024) void lcs_long_kernel(
       }
       if (valid && col > pos) {
         const uint64_t o = orig < b ? out_off + (b - orig - 1u) : rb + (orig - b - 1u);
-        out[o] = (int32_t)cnt;
+        out[o] = tile_value(bt.values, cnt, lane < g.nrows ? bt.len[seq] : 0u, n);
       }
     }
   }
@@ -436,7 +450,7 @@ __global__ __launch_bounds__(256) void lcs_plain_kernel(
     const uint8_t* __restrict__ codes, const uint64_t* __restrict__ dev_off, const uint32_t* __restrict__ len,
     const uint64_t* __restrict__ mask_off, const uint32_t* __restrict__ masks, const PlainRow* __restrict__ rows,
     const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase, const StepRange* __restrict__ ranges,
-    const StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint64_t* __restrict__ work) {
+    const StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint64_t* __restrict__ work, uint32_t values) {
   const uint32_t step = ctl->step;
   const uint32_t rb = ranges[step].begin[4], re = ranges[step].end[4];
   const uint64_t total = ranges[step].plain_pairs;
@@ -502,7 +516,7 @@ __global__ __launch_bounds__(256) void lcs_plain_kernel(
     }
     const uint64_t o = row.orig < b ? row.out_off + (b - row.orig - 1u)
                                     : rowbase[row.rowbase_base + b] + (row.orig - b - 1u);
-    out[o] = (int32_t)cnt;
+    out[o] = tile_value(values, cnt, m, n);
   }
 }
 
@@ -621,7 +635,7 @@ int launch_plain(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_
   hipStream_t s = (hipStream_t)stream;
 #define FAMSA_PLAIN(WW)                                                                                        \
   hipLaunchKernelGGL(lcs_plain_kernel<WW>, grid, block, 0, s, b.codes, b.dev_off, b.len, b.mask_off, b.masks, \
-                     w.prows, w.colmap, w.rowbase, w.ranges, ctl, out, d_work)
+                     w.prows, w.colmap, w.rowbase, w.ranges, ctl, out, d_work, b.values)
   if (w64_max <= 2) FAMSA_PLAIN(2);
   else if (w64_max <= 4) FAMSA_PLAIN(4);
   else if (w64_max <= 8) FAMSA_PLAIN(8);

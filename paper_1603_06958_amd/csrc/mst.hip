@@ -538,6 +538,7 @@ int famsa_mst_consume(void* user, const famsa_lcs_tile* t) {
   famsa_mst_s* m = static_cast<famsa_mst_s*>(user);
   if (!m || !t || t->k != m->k || t->row_begin > t->row_end || t->row_end > m->k) return 1;
   if (t->count && !t->lcs) return 1;
+  if (t->values != FAMSA_LCS_VALUES_LCS) return 1;  // the forest is built from LCS values
   if (t->count != tri_rows(m->k, t->row_begin, t->row_end)) return 1;
   if (hipSetDevice(m->device) != hipSuccess) return 1;
   return m->merge_tile(t, (hipStream_t)t->stream) == 0 ? 0 : 1;
@@ -569,6 +570,19 @@ int famsa_mst_result(const famsa_mst_t* m, uint32_t* u, uint32_t* v, int64_t* lc
   }
   *nedges = n;
   return 0;
+}
+
+int famsa_mst_guide_tree(const famsa_mst_t* m, uint32_t* left, uint32_t* right, int64_t* lcs, int64_t* indel2,
+                         uint32_t* nmerges) {
+  clear_error();
+  if (!m || !nmerges) return set_error(FAMSA_LCS_EINVAL, "NULL argument");
+  const size_t n = std::max<uint32_t>(m->k, 1);
+  std::vector<uint32_t> u(n), v(n);
+  std::vector<int64_t> L(n), D(n);
+  uint32_t ne = 0;
+  int rc = famsa_mst_result(m, u.data(), v.data(), L.data(), D.data(), &ne);
+  if (rc) return rc;
+  return guide_tree(m->k, u.data(), v.data(), L.data(), D.data(), ne, left, right, lcs, indel2, nmerges);
 }
 
 int famsa_mst_get_stats(const famsa_mst_t* m, uint64_t* tiles, uint64_t* rounds) {

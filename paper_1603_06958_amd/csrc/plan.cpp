@@ -460,6 +460,7 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
       tile.count = tl.count;
       tile.lcs = (dev_tiles ? d_out[slot].as<int32_t>() : h_out[slot].as<int32_t>()) + tl.out_off;
       tile.stream = cstream(slot);
+      tile.values = batch.values;
       if (fn(user, &tile) != 0) {
         rc = set_error(FAMSA_LCS_ECANCELED, "tile callback returned nonzero at tile %llu", (unsigned long long)t);
         break;
@@ -547,6 +548,9 @@ int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
   if ((rc = p->host_phase(seq_off, nseq))) return fail(rc);
   if ((rc = p->setup_device())) return fail(rc);
   if ((rc = p->batch.create(codes, seq_off, nseq, o.sigma, p->cs[0]))) return fail(rc);
+  p->batch.values = (o.flags & FAMSA_LCS_OUT_INDEL) ? FAMSA_LCS_VALUES_INDEL
+                    : (o.flags & FAMSA_LCS_OUT_SIM) ? FAMSA_LCS_VALUES_SIM
+                                                    : FAMSA_LCS_VALUES_LCS;
   hipStream_t s = p->cs[0];
   if ((rc = p->upload_work())) return fail(rc);
   if ((rc = p->d_ctl.alloc(2 * sizeof(StepCtl)))) return fail(rc);

@@ -84,8 +84,10 @@ int normalize_options(const famsa_lcs_options* in, Opts* o) {
   if (d.tile_rows < 1) return set_error(FAMSA_LCS_EINVAL, "tile_rows must be >= 1");
   if (d.device < 0) return set_error(FAMSA_LCS_EINVAL, "device %d < 0", d.device);
   const uint32_t known = FAMSA_LCS_PLAIN | FAMSA_LCS_DESCENDING | FAMSA_LCS_DEVICE_TILES | FAMSA_LCS_NO_GRAPH |
-                         FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM;
+                         FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM | FAMSA_LCS_OUT_INDEL | FAMSA_LCS_OUT_SIM;
   if (d.flags & ~known) return set_error(FAMSA_LCS_EINVAL, "unknown flag bits 0x%x", d.flags & ~known);
+  if ((d.flags & FAMSA_LCS_OUT_INDEL) && (d.flags & FAMSA_LCS_OUT_SIM))
+    return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_OUT_INDEL and FAMSA_LCS_OUT_SIM exclude each other");
   if (d.cols_per_item > (1u << 20)) return set_error(FAMSA_LCS_EINVAL, "cols_per_item %u too large", d.cols_per_item);
   o->sigma = d.alphabet_size;
   o->tile_rows = d.tile_rows;
@@ -138,7 +140,7 @@ int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
 
 DeviceBatch DeviceBatchOwner::view() const {
   return DeviceBatch{codes.as<uint8_t>(), dev_off.as<uint64_t>(), sym.as<uint8_t>(), sym_off.as<uint64_t>(),
-                     len.as<uint32_t>(),       mask_off.as<uint64_t>(), masks.as<uint32_t>()};
+                     len.as<uint32_t>(),       mask_off.as<uint64_t>(), masks.as<uint32_t>(), values};
 }
 
 static inline uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

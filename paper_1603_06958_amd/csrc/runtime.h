@@ -80,6 +80,7 @@ struct DeviceBatchOwner {
   std::vector<uint64_t> h_mask_off;  // dword offset of each sequence's masks in `masks`
   std::vector<uint64_t> h_sym_off;   // byte offset of each sequence's column stream in `sym`
   uint32_t nseq = 0, max_len = 0, sigma = 0;
+  uint32_t values = FAMSA_LCS_VALUES_LCS;  // tile contents, from the plan's flags
   uint64_t bytes = 0;
   DeviceBatch view() const;
   // Copies the batch (validated) to the device and builds the masks on `s`.
@@ -171,6 +172,10 @@ int gpu_info(int device, GpuInfo* gi);
 constexpr int kLibStreams = 3;
 constexpr int kCopyStream = 2;
 int lib_stream(int device, int i, hipStream_t* out);
+
+// Single-linkage merge list from a spanning forest's edges (guide_tree.cpp).
+int guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
+               uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* mnum, int64_t* mden, uint32_t* nmerges);
 
 // Class of a group with W dwords per lane (3 = segmented long rows).
 int class_of(uint32_t W, uint32_t sigma);

@@ -110,6 +110,7 @@ int famsa_slink_consume(void* user, const famsa_lcs_tile* t) {
   // previous one began
   if (t->row_end != s->k - s->n) return 1;
   if (t->count && !t->lcs) return 1;
+  if (t->values != FAMSA_LCS_VALUES_LCS) return 1;  // SLINK needs the LCS values
   const uint64_t k = s->k;
   for (uint32_t i = t->row_end; i-- > t->row_begin;) {
     const uint64_t off = famsa::tri_rows(k, t->row_begin, i);
@@ -130,6 +131,27 @@ int famsa_slink_result(const famsa_slink_t* s, uint32_t* pi, int64_t* num, int64
     if (den) den[i] = root ? 0 : s->lambda[p].den;
   }
   return 0;
+}
+
+int famsa_slink_guide_tree(const famsa_slink_t* s, uint32_t* left, uint32_t* right, int64_t* num, int64_t* den,
+                           uint32_t* nmerges) {
+  famsa::clear_error();
+  if (!s || !nmerges) return famsa::set_error(FAMSA_LCS_EINVAL, "NULL argument");
+  const uint32_t k = s->k;
+  std::vector<uint32_t> pi(k), eu, ev;
+  std::vector<int64_t> ln(k), ld(k), en, ed;
+  int rc = famsa_slink_result(s, pi.data(), ln.data(), ld.data());
+  if (rc) return rc;
+  // every point but the root joins the cluster of pi(i) at height lambda(i)
+  for (uint32_t i = 0; i < k; ++i) {
+    if (pi[i] == i) continue;
+    eu.push_back(i);
+    ev.push_back(pi[i]);
+    en.push_back(ln[i]);
+    ed.push_back(ld[i]);
+  }
+  return famsa::guide_tree(k, eu.data(), ev.data(), en.data(), ed.data(), (uint32_t)eu.size(), left, right, num, den,
+                           nmerges);
 }
 
 uint32_t famsa_slink_rows_done(const famsa_slink_t* s) { return s ? s->n : 0; }

@@ -78,6 +78,8 @@ def test_einval_families():
 def test_einval_options():
     assert plan_rc([0], [0, 1], tile_rows=0)[0] == B.EINVAL
     assert plan_rc([0], [0, 1], flags=0x100)[0] == B.EINVAL
+    rc, msg = plan_rc([0], [0, 1], flags=B.OUT_INDEL | B.OUT_SIM)
+    assert rc == B.EINVAL and "exclude" in msg
     L = B.lib()
     o = B.make_options()
     o.struct_size = 4

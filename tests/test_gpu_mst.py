@@ -1,8 +1,9 @@
 """GPU single-linkage consumer (famsa_mst_*): the maximum spanning tree it
 keeps from device tiles equals the unique tie-broken maximum spanning tree of
 the oracle's exact similarities (Kruskal, most similar first, ties by (u, v)),
-and its merge heights and cophenetic similarities equal the oracle's single
-linkage; on a larger family its merge heights equal the host SLINK's."""
+its merge heights and cophenetic similarities equal the oracle's single
+linkage, and its guide tree is the oracle's merge list; on larger families its
+merge heights equal the host SLINK's."""
 from fractions import Fraction
 
 import numpy as np
@@ -15,13 +16,14 @@ from paper_1603_06958_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def gpu_tree(b, **opt):
+def gpu_tree(b, with_guide_tree=False, **opt):
     m = B.Mst(b.lengths())
     with B.Plan.from_batch(b, flags=B.DEVICE_TILES | opt.pop("flags", 0), **opt) as p:
         p.run_native(B.Mst.consume_fn(), m.handle)
     u, v, L, D = m.result()
+    gt = m.guide_tree() if with_guide_tree else None
     m.close()
-    return u, v, L, D
+    return (u, v, L, D, gt) if with_guide_tree else (u, v, L, D)
 
 
 def sim(L, D):
@@ -90,8 +92,10 @@ def test_tree_matches_oracle(seed, k, lo, hi, sigma, R, flags):
         b = inputs.from_sequences(seqs)
     M = oracle.full_matrix(b.codes, b.seq_off, 0, k)
     L = b.lengths()
-    u, v, l, d = gpu_tree(b, tile_rows=R, alphabet_size=max(sigma, 2), flags=flags)
+    u, v, l, d, gt = gpu_tree(b, True, tile_rows=R, alphabet_size=max(sigma, 2), flags=flags)
     assert len(u) == k - 1
+    # the guide tree: the oracle's merge list, ties included
+    assert [(int(a), int(c), sim(x, y)) for a, c, x, y in zip(*gt)] == oracle.guide_tree(M, L)
     got = sorted((int(a), int(c), sim(x, y)) for a, c, x, y in zip(u, v, l, d))
     for a, c, x in got:
         assert int(M[a, c]) == l[list(zip(u, v)).index((a, c))]
