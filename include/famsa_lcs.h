@@ -272,6 +272,47 @@ int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int
                      uint32_t* nmerges);
 
 /* ------------------------------------------------------------------------
+ * Gapped sequence representation (Methods, "Progressive construction of the
+ * alignment", Fig. 1): the form in which the progressive stage moves whole
+ * sequences between profiles and inserts gap columns without copying them.
+ * Each sequence is kept on the device as its symbols behind a guard
+ * (position 0), a gap counter per position -- the gap columns right after
+ * that position's symbol (position 0: leading gaps), as the figure's numbers
+ * have it -- and the tree of column counts dps: with P the positions rounded
+ * up to a power of two (>= 2), leaf P/2 + j counts the columns of positions
+ * 2j and 2j+1 and dps[v] = dps[2v] + dps[2v+1]; dps[1] counts every column,
+ * the guard's included.  Column 0 is the guard's; the alignment's columns
+ * are 1..width.  Calls return when their GPU work is done.
+ * ------------------------------------------------------------------------ */
+typedef struct famsa_gapped_s famsa_gapped_t;
+
+/* nseq sequences (codes, seq_off as for famsa_lcs_plan; lengths <= 65535)
+ * with no gaps, on `device`.  EINVAL on bad input, EDEVICE without a GPU. */
+int famsa_gapped_create(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, int device,
+                        famsa_gapped_t** out);
+/* Insert gap runs into sequences first..first+count-1: run r puts len[r] gap
+ * columns before column col[r].  Columns are those before this call, sorted
+ * ascending, 1 <= col[r] <= width + 1 of every sequence touched (width + 1
+ * appends).  One GPU thread per sequence; O(nruns log n) each. */
+int famsa_gapped_insert(famsa_gapped_t* g, uint32_t first, uint32_t count, const uint32_t* col, const uint32_t* len,
+                        uint32_t nruns);
+/* width[i] = the alignment columns of sequence i (the guard's excluded). */
+int famsa_gapped_width(const famsa_gapped_t* g, uint32_t* width);
+/* pos[q] = the position (0 = guard, i = symbol i) whose span -- its symbol
+ * column and the gap run after it -- holds column col[q] (0..width) of
+ * sequence seq[q]: a walk down the tree per query. */
+int famsa_gapped_locate(famsa_gapped_t* g, const uint32_t* seq, const uint32_t* col, uint32_t nq, uint32_t* pos);
+/* The gapped rows of sequences first..first+count-1 into host memory: row t
+ * (row_bytes apart) gets columns 1..width of sequence first+t, symbol codes
+ * and 0xFF for gaps; bytes past the width are left as they were. */
+int famsa_gapped_decode(famsa_gapped_t* g, uint32_t first, uint32_t count, uint8_t* out, uint64_t row_bytes);
+/* Copies of sequence s's gap counters (npos entries) and tree (ptree
+ * entries, index 0 unused); NULL outputs are skipped. */
+int famsa_gapped_state(famsa_gapped_t* g, uint32_t s, uint32_t* no_gaps, uint32_t* dps, uint32_t* npos,
+                       uint32_t* ptree);
+void famsa_gapped_destroy(famsa_gapped_t* g);
+
+/* ------------------------------------------------------------------------
  * Serving: similarity jobs (each one family) are admitted while their device
  * footprint fits the budget, kept resident, and batched together: every
  * scheduler step gathers the next tiles of all admitted jobs into one launch

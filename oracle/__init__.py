@@ -17,6 +17,10 @@ Contents, each following the FAMSA paper (Methods):
 * ``single_linkage`` -- single-linkage clustering ("Determination of the guide
   tree") by its plain definition: Kruskal's algorithm over all pairs, giving
   the merge heights and the cophenetic similarity of every pair.
+* ``guide_tree`` -- the same clustering as a merge list (the guide tree).
+* ``oracle.gapped`` -- the gapped sequence representation ("Progressive
+  construction of the alignment", Fig. 1) computed from explicit gapped
+  strings.
 
 Readings where the paper is silent: identical sequences (indel 0) have
 similarity +infinity; an empty sequence has LCS 0 with anything.

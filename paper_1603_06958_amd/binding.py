@@ -117,6 +117,20 @@ def lib():
         L.famsa_guide_tree.argtypes = [ctypes.c_uint32, u32p, u32p, i64p, i64p, ctypes.c_uint32, u32p, u32p, i64p,
                                        i64p, u32p]
         L.famsa_guide_tree.restype = ctypes.c_int
+        L.famsa_gapped_create.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(vp)]
+        L.famsa_gapped_create.restype = ctypes.c_int
+        L.famsa_gapped_insert.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, ctypes.c_uint32]
+        L.famsa_gapped_insert.restype = ctypes.c_int
+        L.famsa_gapped_width.argtypes = [vp, u32p]
+        L.famsa_gapped_width.restype = ctypes.c_int
+        L.famsa_gapped_locate.argtypes = [vp, u32p, u32p, ctypes.c_uint32, u32p]
+        L.famsa_gapped_locate.restype = ctypes.c_int
+        L.famsa_gapped_decode.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint64]
+        L.famsa_gapped_decode.restype = ctypes.c_int
+        L.famsa_gapped_state.argtypes = [vp, ctypes.c_uint32, u32p, u32p, u32p, u32p]
+        L.famsa_gapped_state.restype = ctypes.c_int
+        L.famsa_gapped_destroy.argtypes = [vp]
+        L.famsa_gapped_destroy.restype = None
         L.famsa_lcs_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.famsa_lcs_server_create.restype = ctypes.c_int
         L.famsa_lcs_server_submit.argtypes = [vp, u8p, u64p, ctypes.c_uint32, u32p]
@@ -299,6 +313,68 @@ def newick(left, right, k: int, names=None) -> str:
         top.add(k + t)
     roots = sorted(top)
     return (label[roots[0]] if len(roots) == 1 else "(" + ",".join(label[c] for c in roots) + ")") + ";"
+
+
+class Gapped:
+    """Sequences in the gapped representation on the GPU (famsa_gapped_*)."""
+
+    def __init__(self, codes: np.ndarray, seq_off: np.ndarray, device: int = 0):
+        codes = np.ascontiguousarray(codes, np.uint8)
+        off = np.ascontiguousarray(seq_off, np.uint64)
+        h = ctypes.c_void_p()
+        check(lib().famsa_gapped_create(_ptr(codes, ctypes.c_uint8) if codes.size else None,
+                                        _ptr(off, ctypes.c_uint64), off.size - 1, device, ctypes.byref(h)))
+        self.handle = h
+        self.n = int(off.size - 1)
+
+    def insert(self, cols, lens, first: int = 0, count: Optional[int] = None):
+        cols = np.ascontiguousarray(cols, np.uint32)
+        lens = np.ascontiguousarray(lens, np.uint32)
+        count = self.n - first if count is None else count
+        check(lib().famsa_gapped_insert(self.handle, first, count, _ptr(cols, ctypes.c_uint32) if cols.size else None,
+                                        _ptr(lens, ctypes.c_uint32) if lens.size else None, cols.size))
+
+    def width(self) -> np.ndarray:
+        w = np.zeros(max(self.n, 1), np.uint32)
+        check(lib().famsa_gapped_width(self.handle, _ptr(w, ctypes.c_uint32)))
+        return w[:self.n]
+
+    def locate(self, seq, col) -> np.ndarray:
+        seq = np.ascontiguousarray(seq, np.uint32)
+        col = np.ascontiguousarray(col, np.uint32)
+        out = np.zeros(max(seq.size, 1), np.uint32)
+        check(lib().famsa_gapped_locate(self.handle, _ptr(seq, ctypes.c_uint32), _ptr(col, ctypes.c_uint32), seq.size,
+                                        _ptr(out, ctypes.c_uint32)))
+        return out[:seq.size]
+
+    def decode(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        """Rows of symbol codes, 0xFF for gaps (and for padding past a row's width)."""
+        count = self.n - first if count is None else count
+        w = self.width()[first:first + count]
+        rb = int(w.max()) if w.size and w.max() > 0 else 1
+        out = np.full((max(count, 1), rb), 0xFF, np.uint8)
+        check(lib().famsa_gapped_decode(self.handle, first, count, _ptr(out, ctypes.c_uint8), rb))
+        return out[:count]
+
+    def state(self, s: int):
+        n, p = ctypes.c_uint32(), ctypes.c_uint32()
+        check(lib().famsa_gapped_state(self.handle, s, None, None, ctypes.byref(n), ctypes.byref(p)))
+        gaps = np.zeros(n.value, np.uint32)
+        dps = np.zeros(p.value, np.uint32)
+        check(lib().famsa_gapped_state(self.handle, s, _ptr(gaps, ctypes.c_uint32), _ptr(dps, ctypes.c_uint32),
+                                       None, None))
+        return gaps, dps
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().famsa_gapped_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class SLink:
