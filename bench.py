@@ -23,6 +23,9 @@ the kernel's own.  Also reported, in the same JSON line:
   single-linkage consumer (maximum spanning tree of the similarities), and
   the time to turn its tree into the guide tree's merge list;
 * host_slink: the host SLINK consumer's update rate on c2;
+* gapped: the gapped sequence representation over the workload's sequences
+  (one profile-wide round of gap runs inserted into every sequence, every
+  row decoded to host memory);
 * cpu_baseline: the CPU oracle (plain DP) on a bounded sample of the same
   workload's pairs, on the host's cores;
 * c3: batched (persistent, graph-replayed) vs plain per-family launches;
@@ -171,6 +174,28 @@ def run_host_slink():
             "pair_updates_per_s": round(b.pairs() / dt, 1), "threads": 1}
 
 
+def run_gapped(b, nruns=64, seed=11):
+    """Gapped representation over the workload's sequences: one profile-wide
+    round of `nruns` gap runs inserted into every sequence, then every row
+    decoded to host memory."""
+    from paper_1603_06958_amd import binding as B
+    rng = np.random.default_rng(seed)
+    g = B.Gapped(b.codes, b.seq_off)
+    width = int(g.width().min()) + 1
+    cols = np.sort(rng.integers(1, width + 1, nruns)).astype(np.uint32)
+    lens = rng.integers(1, 4, nruns).astype(np.uint32)
+    t0 = time.perf_counter()
+    g.insert(cols, lens)
+    t_ins = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rows = g.decode()
+    t_dec = time.perf_counter() - t0
+    g.close()
+    return {"sequences": b.nseq, "runs": nruns, "insert_ms": round(1e3 * t_ins, 2),
+            "run_updates_per_s": round(b.nseq * nruns / t_ins, 1), "decode_ms": round(1e3 * t_dec, 2),
+            "decoded_bytes": int(rows.nbytes), "decode_host_gb_s": round(rows.nbytes / t_dec / 1e9, 2)}
+
+
 def traffic_per_launch(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     if it was taken from the current kernel source in the bench configuration."""
@@ -308,6 +333,8 @@ def main():
             print(f"[bench] gpu_single_linkage {res['gpu_single_linkage']}", file=sys.stderr, flush=True)
         res["host_slink"] = run_host_slink()
         print(f"[bench] host_slink {res['host_slink']}", file=sys.stderr, flush=True)
+        res["gapped"] = run_gapped(b)
+        print(f"[bench] gapped {res['gapped']}", file=sys.stderr, flush=True)
     if not a.no_c3:
         res["c3"] = run_c3()
         print(f"[bench] c3 {res['c3']}", file=sys.stderr, flush=True)

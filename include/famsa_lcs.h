@@ -270,6 +270,20 @@ void famsa_mst_destroy(famsa_mst_t* mst);
 int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
                      uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* merge_num, int64_t* merge_den,
                      uint32_t* nmerges);
+/* The leaves in depth-first order, left subtree first (order[0..k-1]), and
+ * for every cluster c (0 .. k+nmerges-1) the range first[c] .. first[c] +
+ * size[c] - 1 its leaves take in that order: with the sequences laid out in
+ * this order (e.g. in a famsa_gapped_t) every profile of the progressive
+ * stage is a contiguous range, and two merging profiles are adjacent.
+ * Several roots (a forest) follow each other.  NULL outputs are skipped.
+ * EINVAL if the merges do not each join two current clusters. */
+int famsa_guide_tree_leaf_order(uint32_t k, const uint32_t* left, const uint32_t* right, uint32_t nmerges,
+                                uint32_t* order, uint32_t* first, uint32_t* size);
+/* The tree in Newick form, leaves named by index ("((0,1),2);"; a forest is
+ * wrapped in one more pair of parentheses).  *needed = its length + 1; the
+ * text is written when buf holds that many bytes (buf may be NULL to ask). */
+int famsa_guide_tree_newick(uint32_t k, const uint32_t* left, const uint32_t* right, uint32_t nmerges, char* buf,
+                            uint64_t buf_size, uint64_t* needed);
 
 /* ------------------------------------------------------------------------
  * Gapped sequence representation (Methods, "Progressive construction of the

@@ -117,6 +117,11 @@ def lib():
         L.famsa_guide_tree.argtypes = [ctypes.c_uint32, u32p, u32p, i64p, i64p, ctypes.c_uint32, u32p, u32p, i64p,
                                        i64p, u32p]
         L.famsa_guide_tree.restype = ctypes.c_int
+        L.famsa_guide_tree_leaf_order.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32, u32p, u32p, u32p]
+        L.famsa_guide_tree_leaf_order.restype = ctypes.c_int
+        L.famsa_guide_tree_newick.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32, ctypes.c_char_p,
+                                              ctypes.c_uint64, u64p]
+        L.famsa_guide_tree_newick.restype = ctypes.c_int
         L.famsa_gapped_create.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(vp)]
         L.famsa_gapped_create.restype = ctypes.c_int
         L.famsa_gapped_insert.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, ctypes.c_uint32]
@@ -303,16 +308,33 @@ def guide_tree(k: int, u, v, num, den):
         _ptr(num, ctypes.c_int64) if ne else None, _ptr(den, ctypes.c_int64) if ne else None, ne, l, r, a, b, nm))
 
 
-def newick(left, right, k: int, names=None) -> str:
-    """The merge list as a Newick string (leaves named by index or `names`)."""
-    label = [str(i) if names is None else str(names[i]) for i in range(k)]
-    top = set(range(k))
-    for t, (l, r) in enumerate(zip(left, right)):
-        label.append(f"({label[int(l)]},{label[int(r)]})")
-        top -= {int(l), int(r)}
-        top.add(k + t)
-    roots = sorted(top)
-    return (label[roots[0]] if len(roots) == 1 else "(" + ",".join(label[c] for c in roots) + ")") + ";"
+def newick(left, right, k: int) -> str:
+    """famsa_guide_tree_newick: the merge list in Newick form."""
+    left = np.ascontiguousarray(left, np.uint32)
+    right = np.ascontiguousarray(right, np.uint32)
+    m = left.size
+    lp = _ptr(left, ctypes.c_uint32) if m else None
+    rp = _ptr(right, ctypes.c_uint32) if m else None
+    need = ctypes.c_uint64()
+    check(lib().famsa_guide_tree_newick(k, lp, rp, m, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(int(need.value))
+    check(lib().famsa_guide_tree_newick(k, lp, rp, m, buf, need.value, ctypes.byref(need)))
+    return buf.value.decode()
+
+
+def leaf_order(left, right, k: int):
+    """famsa_guide_tree_leaf_order: (order, first, size)."""
+    left = np.ascontiguousarray(left, np.uint32)
+    right = np.ascontiguousarray(right, np.uint32)
+    m = left.size
+    order = np.zeros(max(k, 1), np.uint32)
+    first = np.zeros(max(k + m, 1), np.uint32)
+    size = np.zeros(max(k + m, 1), np.uint32)
+    check(lib().famsa_guide_tree_leaf_order(k, _ptr(left, ctypes.c_uint32) if m else None,
+                                            _ptr(right, ctypes.c_uint32) if m else None, m,
+                                            _ptr(order, ctypes.c_uint32), _ptr(first, ctypes.c_uint32),
+                                            _ptr(size, ctypes.c_uint32)))
+    return order[:k], first[:k + m], size[:k + m]
 
 
 class Gapped:

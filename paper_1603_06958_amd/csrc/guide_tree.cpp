@@ -14,8 +14,12 @@
 // (holding v) into cluster k + t.  Clusters 0..k-1 are the sequences.
 #include <stdint.h>
 
+#include <stdio.h>
+#include <string.h>
+
 #include <algorithm>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -88,4 +92,107 @@ extern "C" int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v
                                 int64_t* merge_num, int64_t* merge_den, uint32_t* nmerges) {
   famsa::clear_error();
   return famsa::guide_tree(k, u, v, num, den, nedges, left, right, merge_num, merge_den, nmerges);
+}
+
+namespace {
+
+// Children of every cluster and the roots (clusters no merge consumed), after
+// checking that the merge list is well formed.
+int tree_children(uint32_t k, const uint32_t* left, const uint32_t* right, uint32_t nmerges,
+                  std::vector<uint32_t>* roots) {
+  if (nmerges > (k ? k - 1 : 0)) return famsa::set_error(FAMSA_LCS_EINVAL, "%u merges for %u leaves", nmerges, k);
+  if (nmerges && (!left || !right)) return famsa::set_error(FAMSA_LCS_EINVAL, "NULL merge array");
+  std::vector<uint8_t> used(k + nmerges, 0);
+  for (uint32_t t = 0; t < nmerges; ++t) {
+    const uint32_t a = left[t], b = right[t];
+    if (a >= k + t || b >= k + t || a == b || used[a] || used[b])
+      return famsa::set_error(FAMSA_LCS_EINVAL, "merge %u (%u, %u) is not a merge of two current clusters", t, a, b);
+    used[a] = used[b] = 1;
+  }
+  roots->clear();
+  for (uint32_t c = 0; c < k + nmerges; ++c)
+    if (!used[c]) roots->push_back(c);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int famsa_guide_tree_leaf_order(uint32_t k, const uint32_t* left, const uint32_t* right, uint32_t nmerges,
+                                           uint32_t* order, uint32_t* first, uint32_t* size) {
+  famsa::clear_error();
+  std::vector<uint32_t> roots;
+  int rc = tree_children(k, left, right, nmerges, &roots);
+  if (rc) return rc;
+  // leaves in depth-first order, left subtree first; a cluster's leaves are
+  // then one contiguous range
+  const uint32_t nc = k + nmerges;
+  std::vector<uint32_t> f(nc, 0), n(nc, 0);
+  for (uint32_t c = 0; c < k; ++c) n[c] = 1;
+  for (uint32_t t = 0; t < nmerges; ++t) n[k + t] = n[left[t]] + n[right[t]];
+  uint32_t next = 0;
+  for (uint32_t r : roots) {
+    f[r] = next;
+    next += n[r];
+  }
+  for (uint32_t t = nmerges; t-- > 0;) {  // parents before children
+    const uint32_t c = k + t;
+    f[left[t]] = f[c];
+    f[right[t]] = f[c] + n[left[t]];
+  }
+  for (uint32_t c = 0; c < k; ++c)
+    if (order) order[f[c]] = c;
+  for (uint32_t c = 0; c < nc; ++c) {
+    if (first) first[c] = f[c];
+    if (size) size[c] = n[c];
+  }
+  return 0;
+}
+
+extern "C" int famsa_guide_tree_newick(uint32_t k, const uint32_t* left, const uint32_t* right, uint32_t nmerges,
+                                       char* buf, uint64_t buf_size, uint64_t* needed) {
+  famsa::clear_error();
+  if (!needed) return famsa::set_error(FAMSA_LCS_EINVAL, "needed is NULL");
+  std::vector<uint32_t> roots;
+  int rc = tree_children(k, left, right, nmerges, &roots);
+  if (rc) return rc;
+  // iterative walk: emit "(" on entering a merge, "," between its children,
+  // ")" on leaving; leaves by index; several roots are wrapped together
+  std::string out;
+  std::vector<std::pair<uint32_t, int>> st;  // (cluster, children done)
+  char num[16];
+  if (roots.size() != 1) out += '(';
+  for (size_t ri = 0; ri < roots.size(); ++ri) {
+    if (ri) out += ',';
+    st.push_back({roots[ri], 0});
+    while (!st.empty()) {
+      auto& top = st.back();
+      const uint32_t c = top.first;
+      if (c < k) {
+        snprintf(num, sizeof num, "%u", c);
+        out += num;
+        st.pop_back();
+        continue;
+      }
+      const uint32_t t = c - k;
+      if (top.second == 0) {
+        out += '(';
+        top.second = 1;
+        st.push_back({left[t], 0});
+      } else if (top.second == 1) {
+        out += ',';
+        top.second = 2;
+        st.push_back({right[t], 0});
+      } else {
+        out += ')';
+        st.pop_back();
+      }
+    }
+  }
+  if (roots.size() != 1) out += ')';
+  out += ';';
+  *needed = out.size() + 1;
+  if (buf && buf_size >= out.size() + 1) memcpy(buf, out.c_str(), out.size() + 1);
+  else if (buf) return famsa::set_error(FAMSA_LCS_EINVAL, "buffer of %llu bytes, %llu needed",
+                                        (unsigned long long)buf_size, (unsigned long long)(out.size() + 1));
+  return 0;
 }

@@ -196,3 +196,30 @@ def test_host_slink_guide_tree_without_ties_is_the_oracle_tree():
     want = oracle.guide_tree(M, L)
     assert clusters_of(list(zip(left, right)), k) == clusters_of(want, k)
     s.close()
+
+
+@pytest.mark.parametrize("seed,k,lo,hi,sigma", [(1, 12, 0, 12, 2), (3, 25, 20, 60, 20), (9, 1, 3, 3, 2)])
+def test_leaf_order_makes_every_cluster_a_range(seed, k, lo, hi, sigma):
+    M, L = family_matrix(seed, k, lo, hi, sigma)
+    want = oracle.guide_tree(M, L)
+    left = [a for a, _, _ in want]
+    right = [b for _, b, _ in want]
+    order, first, size = B.leaf_order(left, right, k)
+    assert sorted(order) == list(range(k))
+    members = clusters_of(want, k)
+    for c in range(k + len(want)):
+        leaves = {c} if c < k else members[c - k]
+        assert set(order[first[c]:first[c] + size[c]]) == leaves
+    for t, (a, b, _) in enumerate(want):  # merging profiles are adjacent, left first
+        assert first[a] == first[k + t] and first[b] == first[a] + size[a]
+
+
+def test_leaf_order_and_newick_of_a_forest_and_errors():
+    left, right = [3, 0], [4, 1]
+    order, first, size = B.leaf_order(left, right, 5)
+    assert list(order) == [2, 3, 4, 0, 1]
+    with pytest.raises(B.FamsaError):
+        B.leaf_order([0, 0], [1, 2], 3)  # cluster 0 merged twice
+    with pytest.raises(B.FamsaError):
+        B.newick([0], [5], 3)  # no cluster 5 yet
+    assert B.newick([], [], 1) == "0;"
