@@ -1,6 +1,7 @@
-"""Full-size workloads, in the launch configuration bench.py times: seeded
-samples of every tile checked against the oracle one pair at a time, plus
-0 <= LCS <= min(|A|, |B|) over whole tiles."""
+"""Full-size workloads, in the launch configurations bench.py times (c2, c3,
+c4, and the c5 serving jobs): seeded samples of every tile checked against
+the oracle one pair at a time, plus 0 <= LCS <= min(|A|, |B|) over whole
+tiles."""
 import numpy as np
 import pytest
 
@@ -31,10 +32,54 @@ def test_c3_sampled_batched_and_plain_agree():
 
 @pytest.mark.timeout(600)
 def test_c4_sampled_bench_configuration():
+    # the launch configuration bench.py times: 2^28-value steps on one
+    # compute stream, direct launches, autotuned launch shape
     b = inputs.c4()
     s = Sampler(b, per_tile=60, seed=3, bound_check_every=25)
-    with B.Plan.from_batch(b, flags=B.NO_GRAPH) as p:
+    with B.Plan.from_batch(b, flags=B.ONE_STREAM | B.NO_GRAPH, step_values=1 << 28) as p:
+        p.autotune(None)
         p.run(s)
     assert s.ntiles == 98
     assert s.count == b.pairs()
     assert s.check() >= 5000
+
+
+@pytest.mark.timeout(600)
+def test_c4_sampled_two_streams_with_graphs():
+    # the library default (graph replays on two compute streams)
+    b = inputs.c4()
+    s = Sampler(b, per_tile=20, seed=4, bound_check_every=49)
+    with B.Plan.from_batch(b) as p:
+        p.run(s)
+    assert s.ntiles == 98 and s.count == b.pairs()
+    s.check()
+
+
+def test_c5_jobs_sampled_in_the_serving_configuration():
+    # every job of the serving workload through the server as bench.py runs
+    # it (2^24-value steps, 512-row tiles), arrivals replayed at once
+    from paper_1603_06958_amd import serve
+    jobs = inputs.c5(seed=4, njobs=40, rate_per_s=serve.C5_RATE_PER_S)  # the bench's 40 jobs
+    samplers = {}
+
+    def on_tile(jid, t):
+        if jid not in samplers:
+            samplers[jid] = Sampler(jobs[r_ids[jid]].batch, per_tile=30, seed=jid, bound_check_every=7)
+        local = B.Tile.from_buffer_copy(t)  # the job's own batch holds one family
+        local.family = 0
+        samplers[jid](local)
+
+    r_ids = {}
+    srv = serve.Server(step_values=serve.SERVE_STEP_VALUES, tile_rows=serve.SERVE_TILE_ROWS)
+    for i, j in enumerate(jobs):
+        r_ids[srv.submit(j.batch.codes, j.batch.seq_off)] = i
+    active = 1
+    while active:
+        active = srv.step(lambda t: on_tile(int(t.family), t))
+    srv.close()
+    assert len(samplers) == len(jobs)
+    total = 0
+    for jid, smp in samplers.items():
+        assert smp.count == jobs[r_ids[jid]].batch.pairs()
+        total += smp.check()
+    assert total >= 1000
