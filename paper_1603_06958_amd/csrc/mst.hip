@@ -157,9 +157,9 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
     const uint64_t off = row_off(k, r0, i);  // LCS(i, j) at off + j - i - 1
     int32_t L[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 4; ++c) {  // only pairs across components are read: later rounds read little
       const uint32_t j = jb + 64u * c + lane;
-      L[c] = (j > i && j < m.k) ? tile[off + (j - i - 1u)] : 0;
+      L[c] = (j > i && j < m.k && cc[c] != ci) ? tile[off + (j - i - 1u)] : 0;
     }
     uint64_t rk = 0, ri = ~0ull;
     int32_t rL = 0;
