@@ -16,15 +16,15 @@
 // against a run of column positions.  One workgroup does an item: the
 // group's masks go to LDS, and each wave takes one column sequence at a time
 // and streams it through the recurrence for all 64 rows at once (the
-// column's symbol is the same for the whole wave, so it comes from scalar
-// loads).  Two layouts:
+// column's symbol is the same for the whole wave: it is read from the
+// column's pre-scaled symbol stream at a wave-uniform address).  Two layouts:
 //   family mode -- a family whose whole upper triangle fits one launch step
 //     is sorted by length (longest first); rows and columns are positions in
 //     that order and a lane needs the columns after its own position, so
 //     every unordered pair is computed once;
-//   tile mode -- a family too large for one step is done one row tile at a
-//     time: the tile's rows are sorted by length and need the columns (in the
-//     caller's order) after their own index.
+//   tile mode -- a family too large for one step is done row tile by row
+//     tile: the rows of a step's tiles are pooled and sorted by length, and
+//     each needs the columns (in the caller's order) after its own index.
 #pragma once
 #include <stdint.h>
 

@@ -1,11 +1,11 @@
 // famsa_lcs_plan / famsa_lcs_tiles / famsa_lcs_release: the C-ABI over the
 // runtime.  A plan owns the resident batch, the descriptor arrays of every
 // launch step, two device step buffers, two pinned host buffers, and (unless
-// disabled) two instantiated hipGraphs -- one per compute stream -- that
-// replay a step's launches.  Steps alternate between the two streams so one
-// step's tail overlaps the next step's head, while a copy stream moves
-// finished steps to pinned memory and the caller's thread runs the tile
-// callbacks.
+// disabled) instantiated hipGraphs -- one per compute stream and launch
+// signature -- that replay a step's launches.  Steps alternate between the
+// device's two shared compute streams so one step's tail overlaps the next
+// step's head, while the shared copy stream moves finished steps to pinned
+// memory and the caller's thread runs the tile callbacks.
 #include <stdio.h>
 #include <string.h>
 
