@@ -9,7 +9,11 @@
  * (Methods, "Determination of the guide tree").  This library computes the
  * exact int32 LCS length of every pair i < j inside each family on one GPU
  * and hands the results to the caller as row tiles, so the k x k matrix is
- * never stored.
+ * never stored.  Around that core: tiles of indel distances or similarities
+ * instead of LCS values; two single-linkage consumers (SLINK on the host, an
+ * exact maximum spanning forest on the GPU) and the guide tree they give;
+ * the gapped sequence representation the progressive stage builds profiles
+ * with; and a continuous-batching server for many families.
  *
  * Conventions for every call:
  *  - Functions return 0 (FAMSA_LCS_OK) or a negative famsa_lcs_status; the
