@@ -33,11 +33,10 @@ def build(verbose: bool = False) -> str:
             continue
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc(), "-c", path, "-o", obj] + common
-        if src.endswith(".hip"):
-            cmd += ["-x", "hip", "--offload-arch=" + ARCH,
-                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-        else:
-            cmd += ["-x", "hip", "--offload-arch=" + ARCH]
+        if src.endswith(".hip"):  # device code: HIP for gfx950
+            cmd += ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+        else:  # host code calling the HIP runtime
+            cmd += ["--offload-arch=" + ARCH]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

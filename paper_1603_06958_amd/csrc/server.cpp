@@ -208,8 +208,9 @@ int famsa_lcs_server_s::issue(int si) {
     const uint64_t need = (uint64_t)sl.exec.plain_blocks * kPlainBlock * sl.exec.w64max_plain * 8;
     if (sl.d_plainwork.bytes < need && (rc = sl.d_plainwork.alloc(need))) return rc;
   }
+  // codes, sym and masks are null: the step's offsets are absolute device addresses
   DeviceBatch b{nullptr, sl.d_devoff.as<uint64_t>(),  nullptr, sl.d_symoff.as<uint64_t>(),
-                sl.d_len.as<uint32_t>(), sl.d_maskoff.as<uint64_t>(), nullptr};
+                sl.d_len.as<uint32_t>(), sl.d_maskoff.as<uint64_t>(), nullptr, FAMSA_LCS_VALUES_LCS};
   DeviceWork w{sl.d_groups.as<GroupDesc>(), sl.d_lanes.as<LaneDesc>(), sl.d_items.as<ItemDesc>(),
                sl.d_prows.as<PlainRow>(), sl.d_colmap.as<uint32_t>(), sl.d_rowbase.as<uint64_t>(),
                sl.d_ranges.as<StepRange>()};
