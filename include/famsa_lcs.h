@@ -63,8 +63,7 @@ typedef enum famsa_lcs_status {
                                         one captured hipGraph per launch step */
 #define FAMSA_LCS_NO_AUTOTUNE  0x10u /* use the built-in launch parameters; ignore the tuning cache */
 #define FAMSA_LCS_ONE_STREAM   0x20u /* run every launch step on one compute stream (by default consecutive steps
-                                        overlap on two); per-kernel timings then exclude the other stream, and
-                                        rows of 513..896 residues join the launch of rows of 257..512 */
+                                        overlap on two); per-kernel timings then exclude the other stream */
 #define FAMSA_LCS_OUT_INDEL    0x40u /* tiles hold indel = |A| + |B| - 2 LCS (int32) instead of LCS */
 #define FAMSA_LCS_OUT_SIM      0x80u /* tiles hold the similarity LCS / indel^2 as float32 (the float rounding
                                         of the correctly rounded double; +infinity when indel = 0) instead of
@@ -178,9 +177,8 @@ int famsa_lcs_plan_dry_run(const uint8_t* codes, const uint64_t* seq_off, uint32
  * a graph (FAMSA_LCS_NO_GRAPH or FAMSA_LCS_PLAIN); step_ms is always there. */
 typedef struct famsa_lcs_stats {
   double kernel_ms[5];     /* summed duration per kernel: [0] rows of <= 256 residues, [1] <= 512, [2] <= 896
-                              (<= 512 with more than 20 symbols; under FAMSA_LCS_ONE_STREAM these rows run in
-                              the launch of [1]), [3] longer rows, in segments, [4] plain one-pair-per-lane
-                              baseline (FAMSA_LCS_PLAIN) */
+                              (<= 512 with more than 20 symbols), [3] longer rows, in segments,
+                              [4] plain one-pair-per-lane baseline (FAMSA_LCS_PLAIN) */
   uint64_t launches[5];
   uint64_t cells[5];       /* algorithmic cells |A||B| assigned to each kernel over the whole plan */
   double step_ms;          /* summed device time of the launch steps (all kernels of a step) */

@@ -211,9 +211,7 @@ __global__ __launch_bounds__(1024) void lcs_fast_kernel(
     const ItemDesc* __restrict__ items, const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase,
     const StepRange* __restrict__ ranges, StepCtl* __restrict__ ctl, int32_t* __restrict__ out, uint32_t sigma) {
   constexpr int WLO = CLS == 0 ? 1 : 4 * kClassQMax[CLS > 0 ? CLS - 1 : 0] + 1;
-  // class 1 also takes class 2's widths (rows of 17..28 dwords) when a plan
-  // runs them in the class-1 launch
-  constexpr int WHI = 4 * kClassQMax[CLS == 1 ? 2 : CLS];
+  constexpr int WHI = 4 * kClassQMax[CLS];
   extern __shared__ uint4 lds4[];
   char* lds = reinterpret_cast<char*>(lds4);
   __shared__ uint32_t s_item;

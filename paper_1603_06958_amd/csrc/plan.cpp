@@ -534,7 +534,6 @@ int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
   if ((rc = gpu_info(o.device, &p->gi))) return fail(rc);
   if (!(o.flags & FAMSA_LCS_NO_AUTOTUNE)) tune_lookup(p->gi, o.sigma, &p->lp);
   if (o.cols_per_item) p->lp.cols_per_item = o.cols_per_item;
-  p->lp.wide_in_class1 = (o.flags & FAMSA_LCS_ONE_STREAM) != 0;
 
   // budget: batch + descriptors + 2 step buffers (+ plain scratch)
   size_t freeb = 0, totalb = 0;
@@ -598,7 +597,6 @@ int famsa_lcs_plan_dry_run(const uint8_t* codes, const uint64_t* seq_off, uint32
   p.opt = o;
   p.fam_off = fo;
   if (o.cols_per_item) p.lp.cols_per_item = o.cols_per_item;
-  p.lp.wide_in_class1 = (o.flags & FAMSA_LCS_ONE_STREAM) != 0;
   if ((rc = p.host_phase(seq_off, nseq))) return rc;
   p.batch.max_len = maxlen;
   if (dump_path && (rc = p.dump(dump_path))) return rc;

@@ -220,11 +220,11 @@ int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uin
   return 0;
 }
 
-int class_of(uint32_t W, uint32_t sigma, bool wide_in_class1) {
+int class_of(uint32_t W, uint32_t sigma) {
   const uint32_t Q = (W + 3) / 4;
   if (fast_lds_bytes(sigma, Q) + kLdsReserve > g_max_lds) return 3;
   for (int c = 0; c < 3; ++c)
-    if (Q <= (uint32_t)kClassQMax[c]) return (c == 2 && wide_in_class1) ? 1 : c;
+    if (Q <= (uint32_t)kClassQMax[c]) return c;
   return 3;
 }
 
@@ -297,7 +297,7 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
         g.fam_base = fb;
         g.colmap_base = cm_base;
         g.rowbase_base = rb_base;
-        const int cls = class_of(W, sigma, lp.wide_in_class1);
+        const int cls = class_of(W, sigma);
         for (uint32_t l = 0; l < nrows; ++l) {
           const uint32_t a = perm[P + l];
           LaneDesc ld{wl.rowbase[rb_base + a], fb + a, P + l, a, 0};
@@ -339,7 +339,7 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
         g.fam_base = fb;
         g.colmap_base = kNoMap;
         g.rowbase_base = kNoMap;
-        const int cls = plain_only ? 4 : class_of(W, sigma, lp.wide_in_class1);
+        const int cls = plain_only ? 4 : class_of(W, sigma);
         for (uint32_t l = 0; l < nrows; ++l) {
           const uint32_t i = rows[ord[P + l]];
           LaneDesc ld{rowoff[ord[P + l]], fb + i, i, i, 0};
@@ -366,7 +366,7 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
   for (const PendingGroup& pg : pend) {
     const uint32_t gi = (uint32_t)wl.groups.size();
     wl.groups.push_back(pg.g);
-    const int cls = class_of(pg.g.W, sigma, lp.wide_in_class1);
+    const int cls = class_of(pg.g.W, sigma);
     const uint32_t q = (pg.g.W + 3) / 4;
     if (cls < 3) {
       wl.qmax[cls] = std::max(wl.qmax[cls], q);

@@ -99,11 +99,6 @@ struct TileWork {
 struct LaunchParams {
   uint32_t waves[4] = {4, 8, 16, 16};  // wavefronts per workgroup per class (3 = long rows)
   uint32_t cols_per_item = 256;
-  // Rows of class 2's widths (17..28 dwords) go into the class-1 launch.
-  // Set for one compute stream, where nothing overlaps a short class-2
-  // launch's ramp and tail; with two streams the other stream's launches
-  // fill them, and a class-1 launch sized for wide rows would hold more LDS.
-  bool wide_in_class1 = false;
 };
 
 // The launches one step needs: for each fast class the quad count of its
@@ -183,7 +178,7 @@ int guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* 
                uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* mnum, int64_t* mden, uint32_t* nmerges);
 
 // Class of a group with W dwords per lane (3 = segmented long rows).
-int class_of(uint32_t W, uint32_t sigma, bool wide_in_class1 = false);
+int class_of(uint32_t W, uint32_t sigma);
 
 // Executes the launches of one step for a set of descriptor arrays.
 struct StepExec {

@@ -163,14 +163,3 @@ def test_torch_stream_and_repeat():
     for key in t1:
         assert np.array_equal(t1[key], t2[key])
     check_all_tiles(b, t1, 1024)
-
-
-@pytest.mark.parametrize("flags,opt", [(B.ONE_STREAM, {}), (B.ONE_STREAM | B.NO_GRAPH, dict(tile_rows=70,
-                                                                                              step_values=9000))])
-def test_one_stream_wide_rows_in_class_1(flags, opt):
-    # under one compute stream, rows of 17..28 dwords run in the class-1 launch
-    b = inputs.random_family(200, 200, 880, 7)
-    R = opt.get("tile_rows", 1024)
-    tiles, _, st = run(b, flags=flags, **opt)
-    check_all_tiles(b, tiles, R)
-    assert st.cells[2] == 0 and st.cells[1] > 0

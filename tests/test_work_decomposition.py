@@ -26,9 +26,6 @@ CASES = {
     "sigma32": (lambda: inputs.random_family(50, 0, 900, 4, alphabet=32), dict(alphabet_size=32, tile_rows=9)),
     "small_cols": (lambda: inputs.random_family(300, 0, 500, 5), dict(tile_rows=64, step_values=9000,
                                                                       cols_per_item=16)),
-    "wide_family_one_stream": (lambda: inputs.random_family(200, 200, 880, 7), dict(flags=B.ONE_STREAM)),
-    "wide_tiles_one_stream": (lambda: inputs.random_family(200, 200, 880, 8),
-                              dict(tile_rows=70, step_values=9000, flags=B.ONE_STREAM)),
 }
 
 
@@ -40,10 +37,6 @@ def test_coverage(name):
     assert info.pairs == b.pairs()
     assert info.cells == b.cells()
     check_coverage(d)
-    if opt.get("flags", 0) & B.ONE_STREAM:  # rows of 17..28 dwords join class 1
-        assert all(r["begin"][2] == r["end"][2] for r in d["ranges"])
-        W = [int(g["W"]) for g in d["groups"]]
-        assert any(16 < w <= 28 for w in W)
 
 
 def test_multi_family_coverage_and_whole_families():
