@@ -19,6 +19,8 @@ the kernel's own.  Also reported, in the same JSON line:
   from the current kernel source and this configuration, else null;
 * two_streams: the same pass with consecutive steps on two compute streams
   (the library default), where one step's tail overlaps the next step;
+* similarity_tiles: the same pass delivering float32 similarities instead of
+  LCS values (the kernels' epilogue computes them);
 * gpu_single_linkage: the pass with device tiles feeding the GPU exact
   single-linkage consumer (maximum spanning tree of the similarities), and
   the time to turn its tree into the guide tree's merge list;
@@ -328,6 +330,11 @@ def main():
                               "ms_per_step": round(1e3 * min(t2), 2),
                               "note": "same pass, consecutive steps on two compute streams (library default)"}
         print(f"[bench] two_streams {res['two_streams']}", file=sys.stderr, flush=True)
+        _, t3, _, _ = run_main(b, 2, 1, flags=B.OUT_SIM, tune=True)
+        res["similarity_tiles"] = {"value": round(cells / min(t3) / 1e9, 1), "unit": "GCUPS",
+                                   "ms_per_step": round(1e3 * min(t3), 2),
+                                   "note": "same pass delivering float32 LCS/indel^2 tiles (FAMSA_LCS_OUT_SIM)"}
+        print(f"[bench] similarity_tiles {res['similarity_tiles']}", file=sys.stderr, flush=True)
         if a.workload == "c4":
             res["gpu_single_linkage"] = run_gpu_single_linkage(b)
             print(f"[bench] gpu_single_linkage {res['gpu_single_linkage']}", file=sys.stderr, flush=True)
