@@ -274,6 +274,16 @@ void famsa_mst_destroy(famsa_mst_t* mst);
 int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
                      uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* merge_num, int64_t* merge_den,
                      uint32_t* nmerges);
+/* The maximum spanning forest of any nedges edges (u, v, num/den as above,
+ * cycles allowed) under the same order: most similar first, equal
+ * similarities by the pair (min, max).  Out arrays hold up to k-1 edges,
+ * written as (min, max); *nout is their number.  Because the forest of a
+ * union of edge sets equals the forest of the union of their forests, the
+ * forests that several consumers (one per GPU, say) build from disjoint
+ * shares of a family's tiles merge here into the forest of all its pairs. */
+int famsa_spanning_forest(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
+                          uint64_t nedges, uint32_t* out_u, uint32_t* out_v, int64_t* out_num, int64_t* out_den,
+                          uint32_t* nout);
 /* The leaves in depth-first order, left subtree first (order[0..k-1]), and
  * for every cluster c (0 .. k+nmerges-1) the range first[c] .. first[c] +
  * size[c] - 1 its leaves take in that order: with the sequences laid out in

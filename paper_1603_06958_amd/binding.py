@@ -117,6 +117,9 @@ def lib():
         L.famsa_guide_tree.argtypes = [ctypes.c_uint32, u32p, u32p, i64p, i64p, ctypes.c_uint32, u32p, u32p, i64p,
                                        i64p, u32p]
         L.famsa_guide_tree.restype = ctypes.c_int
+        L.famsa_spanning_forest.argtypes = [ctypes.c_uint32, u32p, u32p, i64p, i64p, ctypes.c_uint64, u32p, u32p,
+                                            i64p, i64p, u32p]
+        L.famsa_spanning_forest.restype = ctypes.c_int
         L.famsa_guide_tree_leaf_order.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32, u32p, u32p, u32p]
         L.famsa_guide_tree_leaf_order.restype = ctypes.c_int
         L.famsa_guide_tree_newick.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32, ctypes.c_char_p,
@@ -306,6 +309,23 @@ def guide_tree(k: int, u, v, num, den):
     return _merges(k, lambda l, r, a, b, nm: lib().famsa_guide_tree(
         k, _ptr(u, ctypes.c_uint32) if ne else None, _ptr(v, ctypes.c_uint32) if ne else None,
         _ptr(num, ctypes.c_int64) if ne else None, _ptr(den, ctypes.c_int64) if ne else None, ne, l, r, a, b, nm))
+
+
+def spanning_forest(k: int, u, v, num, den):
+    """famsa_spanning_forest: (u, v, num, den) of the maximum spanning forest of the edges."""
+    u, v = np.ascontiguousarray(u, np.uint32), np.ascontiguousarray(v, np.uint32)
+    num, den = np.ascontiguousarray(num, np.int64), np.ascontiguousarray(den, np.int64)
+    n = max(k - 1, 1)
+    ou, ov = np.zeros(n, np.uint32), np.zeros(n, np.uint32)
+    on, od = np.zeros(n, np.int64), np.zeros(n, np.int64)
+    cnt = ctypes.c_uint32()
+    ne = u.size
+    check(lib().famsa_spanning_forest(k, _ptr(u, ctypes.c_uint32) if ne else None, _ptr(v, ctypes.c_uint32) if ne else None,
+                                      _ptr(num, ctypes.c_int64) if ne else None, _ptr(den, ctypes.c_int64) if ne else None,
+                                      ne, _ptr(ou, ctypes.c_uint32), _ptr(ov, ctypes.c_uint32), _ptr(on, ctypes.c_int64),
+                                      _ptr(od, ctypes.c_int64), ctypes.byref(cnt)))
+    m = int(cnt.value)
+    return ou[:m], ov[:m], on[:m], od[:m]
 
 
 def newick(left, right, k: int) -> str:

@@ -85,7 +85,67 @@ int guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* 
   return 0;
 }
 
+// Maximum spanning forest of any edge set under the same total order
+// (Kruskal: most similar first, equal similarities by the pair).  The
+// forest of a union of edge sets is the forest of the union of their
+// forests, so forests of disjoint shards of the tiles merge into the forest
+// of all the tiles.
+int spanning_forest(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
+                    uint64_t nedges, uint32_t* ou, uint32_t* ov, int64_t* onum, int64_t* oden, uint32_t* nout) {
+  if (!nout) return set_error(FAMSA_LCS_EINVAL, "nout is NULL");
+  *nout = 0;
+  if (nedges && (!u || !v || !num || !den)) return set_error(FAMSA_LCS_EINVAL, "NULL edge array");
+  std::vector<uint32_t> eu(nedges), ev(nedges);
+  std::vector<uint64_t> order(nedges);
+  for (uint64_t e = 0; e < nedges; ++e) {
+    if (u[e] >= k || v[e] >= k || u[e] == v[e])
+      return set_error(FAMSA_LCS_EINVAL, "edge %llu (%u, %u) is not a pair of distinct sequences < %u",
+                       (unsigned long long)e, u[e], v[e], k);
+    if (den[e] < 0 || (den[e] > 0 && num[e] < 0))
+      return set_error(FAMSA_LCS_EINVAL, "edge %llu: similarity %lld/%lld is not >= 0", (unsigned long long)e,
+                       (long long)num[e], (long long)den[e]);
+    eu[e] = std::min(u[e], v[e]);
+    ev[e] = std::max(u[e], v[e]);
+    order[e] = e;
+  }
+  std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
+    if (more_similar(num[a], den[a], num[b], den[b])) return true;
+    if (more_similar(num[b], den[b], num[a], den[a])) return false;
+    return eu[a] != eu[b] ? eu[a] < eu[b] : ev[a] < ev[b];
+  });
+  std::vector<uint32_t> parent(k);
+  std::iota(parent.begin(), parent.end(), 0u);
+  auto find = [&](uint32_t x) {
+    while (parent[x] != x) {
+      parent[x] = parent[parent[x]];
+      x = parent[x];
+    }
+    return x;
+  };
+  uint32_t n = 0;
+  for (uint64_t t = 0; t < nedges; ++t) {
+    const uint64_t e = order[t];
+    const uint32_t a = find(eu[e]), b = find(ev[e]);
+    if (a == b) continue;  // closes a cycle: not in the forest
+    parent[a] = b;
+    if (ou) ou[n] = eu[e];
+    if (ov) ov[n] = ev[e];
+    if (onum) onum[n] = num[e];
+    if (oden) oden[n] = den[e];
+    ++n;
+  }
+  *nout = n;
+  return 0;
+}
+
 }  // namespace famsa
+
+extern "C" int famsa_spanning_forest(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num,
+                                     const int64_t* den, uint64_t nedges, uint32_t* out_u, uint32_t* out_v,
+                                     int64_t* out_num, int64_t* out_den, uint32_t* nout) {
+  famsa::clear_error();
+  return famsa::spanning_forest(k, u, v, num, den, nedges, out_u, out_v, out_num, out_den, nout);
+}
 
 extern "C" int famsa_guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num,
                                 const int64_t* den, uint32_t nedges, uint32_t* left, uint32_t* right,

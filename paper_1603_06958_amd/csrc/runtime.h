@@ -173,6 +173,9 @@ constexpr int kLibStreams = 3;
 constexpr int kCopyStream = 2;
 int lib_stream(int device, int i, hipStream_t* out);
 
+// Maximum spanning forest of an edge set (guide_tree.cpp).
+int spanning_forest(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
+                    uint64_t nedges, uint32_t* ou, uint32_t* ov, int64_t* onum, int64_t* oden, uint32_t* nout);
 // Single-linkage merge list from a spanning forest's edges (guide_tree.cpp).
 int guide_tree(uint32_t k, const uint32_t* u, const uint32_t* v, const int64_t* num, const int64_t* den,
                uint32_t nedges, uint32_t* left, uint32_t* right, int64_t* mnum, int64_t* mden, uint32_t* nmerges);

@@ -4,6 +4,7 @@ the oracle's exact similarities (Kruskal, most similar first, ties by (u, v)),
 its merge heights and cophenetic similarities equal the oracle's single
 linkage, and its guide tree is the oracle's merge list; on larger families its
 merge heights equal the host SLINK's."""
+import ctypes
 from fractions import Fraction
 
 import numpy as np
@@ -118,3 +119,32 @@ def test_heights_match_host_slink_c2_like(k, R):
     slink_h = sorted(sim(n, q) for n, q in zip(num, den) if not (n == -1 and q == 0))
     assert len(u) == k - 1
     assert sorted(sim(x, y) for x, y in zip(l, d)) == slink_h
+
+
+@pytest.mark.parametrize("k,R,nshard", [(300, 16, 2), (3000, 256, 3)])
+def test_sharded_consumers_merge_to_the_same_tree(k, R, nshard):
+    # one GPU standing in for several: device tiles dealt round-robin to
+    # `nshard` consumers (each keeps the forest of its own share), forests
+    # merged on the host; the result is the tree of all pairs
+    b = inputs.c2(k=k)
+    shards = [B.Mst(b.lengths()) for _ in range(nshard)]
+    consume = B.lib().famsa_mst_consume
+    seen = [0] * nshard
+
+    def deal(t):
+        s = int(t.tile_index) % nshard
+        seen[s] += 1
+        return consume(shards[s].handle, ctypes.byref(t))
+
+    with B.Plan.from_batch(b, tile_rows=R, flags=B.DEVICE_TILES) as p:
+        p.run(deal)
+    parts = [m.result() for m in shards]
+    for m in shards:
+        m.close()
+    assert all(seen)
+    cat = [np.concatenate([q[x] for q in parts]) for x in range(4)]
+    mu, mv, mL, mD = B.spanning_forest(k, *cat)
+    u, v, L, D = gpu_tree(b, tile_rows=R)
+    assert sorted(zip(mu.tolist(), mv.tolist(), mL.tolist(), mD.tolist())) == \
+        sorted(zip(u.tolist(), v.tolist(), L.tolist(), D.tolist()))
+    assert len(mu) == k - 1

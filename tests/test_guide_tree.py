@@ -223,3 +223,30 @@ def test_leaf_order_and_newick_of_a_forest_and_errors():
     with pytest.raises(B.FamsaError):
         B.newick([0], [5], 3)  # no cluster 5 yet
     assert B.newick([], [], 1) == "0;"
+
+
+@pytest.mark.parametrize("seed,k,lo,hi,sigma", [(1, 12, 0, 12, 2), (3, 25, 20, 60, 20), (7, 40, 0, 30, 3)])
+def test_spanning_forest_of_all_pairs_and_of_merged_shards(seed, k, lo, hi, sigma):
+    M, L = family_matrix(seed, k, lo, hi, sigma)
+    want = oracle_edges(M, L)
+    ii, jj = np.triu_indices(k, 1)
+    lcs = M[ii, jj].astype(np.int64)
+    d2 = (L[ii].astype(np.int64) + L[jj] - 2 * lcs) ** 2
+    u, v, n, d = B.spanning_forest(k, ii, jj, lcs, d2)
+    assert list(zip(u.tolist(), v.tolist(), n.tolist(), d.tolist())) == want
+    # forests of disjoint shards of the pairs, merged, give the same forest
+    rng = np.random.default_rng(seed)
+    shard = rng.integers(0, 3, ii.size)
+    parts = [B.spanning_forest(k, ii[shard == s], jj[shard == s], lcs[shard == s], d2[shard == s]) for s in range(3)]
+    cat = [np.concatenate([p[x] for p in parts]) for x in range(4)]
+    u2, v2, n2, d2_ = B.spanning_forest(k, *cat)
+    assert list(zip(u2.tolist(), v2.tolist(), n2.tolist(), d2_.tolist())) == want
+
+
+def test_spanning_forest_errors():
+    with pytest.raises(B.FamsaError):
+        B.spanning_forest(3, [0], [3], [1], [1])
+    with pytest.raises(B.FamsaError):
+        B.spanning_forest(3, [1], [1], [1], [1])
+    u, v, n, d = B.spanning_forest(4, [0, 1, 0, 2], [1, 0, 1, 3], [1, 1, 1, 1], [4, 4, 4, 0])
+    assert list(zip(u, v)) == [(2, 3), (0, 1)]  # +inf first; the duplicate pairs close cycles
