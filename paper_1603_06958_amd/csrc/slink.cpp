@@ -4,10 +4,9 @@
 //
 // Similarity of a pair (Methods, "Pairwise similarities calculation"):
 //   indel = |A| + |B| - 2 LCS,   similarity = LCS / indel^2,
-// kept as the exact rational (LCS, indel^2); indel = 0 (identical sequences,
-// including two empty ones) is +infinity.  Two similarities are compared by
-// cross-multiplying in int64, exact for lengths up to FAMSA_LCS_MAX_LEN
-// (numerators <= 65535, denominators <= 131070^2).
+// kept exactly as (LCS, indel); indel = 0 (identical sequences, including
+// two empty ones) is +infinity.  Two similarities are compared by an integer
+// key that orders them exactly (below).
 //
 // SLINK (Sibson 1973) inserts points one by one and keeps the pointer
 // representation: for each inserted point, pi = the later-inserted point it
@@ -26,20 +25,21 @@
 
 namespace {
 
-struct Sim {
-  int64_t num, den;  // den == 0: +infinity; the "never joins" value is (-1, 1)
-};
-
-inline bool sim_less(const Sim& a, const Sim& b) {  // a strictly less similar than b
-  if (a.den == 0) return false;
-  if (b.den == 0) return true;
-  return a.num * b.den < b.num * a.den;
+// Similarities are ordered by a 64-bit key: the bits of the correctly rounded
+// double LCS / indel^2, plus one (+infinity for indel 0); 0 is the "never
+// joins" value below every similarity.  For lengths up to FAMSA_LCS_MAX_LEN
+// two different ratios differ by a relative 2^-50 or more, so their doubles
+// differ and keep the exact order; equal ratios give equal keys.  The exact
+// rational is kept beside each key (LCS in the low and indel in the high 32
+// bits) for the result.
+inline uint64_t sim_key(int64_t L, int64_t d) {
+  const double s = d == 0 ? __builtin_inf() : (double)L / ((double)d * (double)d);
+  uint64_t bits;
+  memcpy(&bits, &s, 8);
+  return bits + 1;
 }
 
-inline Sim sim_of(int64_t L, int64_t la, int64_t lb) {
-  const int64_t d = la + lb - 2 * L;
-  return Sim{L, d * d};
-}
+inline uint64_t pack_ld(int64_t L, int64_t d) { return ((uint64_t)d << 32) | (uint64_t)L; }
 
 }  // namespace
 
@@ -47,32 +47,46 @@ struct famsa_slink_s {
   uint32_t k = 0;
   std::vector<uint32_t> len;   // by original index
   std::vector<uint32_t> pi;    // by insertion order p (point p is original index k-1-p)
-  std::vector<Sim> lambda, M;
+  std::vector<uint64_t> lk, mk;  // keys of lambda and M
+  std::vector<uint64_t> lv, mv;  // their (LCS, indel) values
   uint32_t n = 0;              // points inserted
   void insert_row(const int32_t* row);  // row: LCS(i, j) for j = i+1..k-1, i = k-1-n
 };
 
 void famsa_slink_s::insert_row(const int32_t* row) {
   const uint32_t i_new = k - 1 - n;
-  // distances to the inserted points p = 0..n-1 (original j = k-1-p)
+  const int64_t li = len[i_new];
+  uint64_t* __restrict__ Mk = mk.data();
+  uint64_t* __restrict__ Mv = mv.data();
+  uint64_t* __restrict__ Lk = lk.data();
+  uint64_t* __restrict__ Lv = lv.data();
+  uint32_t* __restrict__ P = pi.data();
+  // similarities to the inserted points p = 0..n-1 (original j = k-1-p)
   for (uint32_t p = 0; p < n; ++p) {
     const uint32_t j = k - 1 - p;
-    M[p] = sim_of(row[j - i_new - 1], len[i_new], len[j]);
+    const int64_t L = row[j - i_new - 1];
+    const int64_t d = li + (int64_t)len[j] - 2 * L;
+    Mk[p] = sim_key(L, d);
+    Mv[p] = pack_ld(L, d);
   }
-  pi[n] = n;
-  lambda[n] = Sim{-1, 1};
+  P[n] = n;
+  Lk[n] = 0;
+  Lv[n] = 0;
+  // with similarities "lambda(p) >= M(p)" of the distance form reads "lambda(p)
+  // is no more similar than M(p)"; the updates are written as selects, since
+  // which way each point goes is data dependent
   for (uint32_t p = 0; p < n; ++p) {
-    const uint32_t q = pi[p];
-    if (!sim_less(M[p], lambda[p])) {  // lambda(p) no more similar than M(p)
-      if (sim_less(M[q], lambda[p])) M[q] = lambda[p];
-      lambda[p] = M[p];
-      pi[p] = n;
-    } else {
-      if (sim_less(M[q], M[p])) M[q] = M[p];
-    }
+    const uint32_t q = P[p];  // q > p: a later point
+    const bool c = Mk[p] >= Lk[p];
+    const uint64_t ck = c ? Lk[p] : Mk[p], cv = c ? Lv[p] : Mv[p];
+    const bool up = Mk[q] < ck;
+    Mk[q] = up ? ck : Mk[q];
+    Mv[q] = up ? cv : Mv[q];
+    Lk[p] = c ? Mk[p] : Lk[p];
+    Lv[p] = c ? Mv[p] : Lv[p];
+    P[p] = c ? n : q;
   }
-  for (uint32_t p = 0; p < n; ++p)
-    if (!sim_less(lambda[pi[p]], lambda[p])) pi[p] = n;
+  for (uint32_t p = 0; p < n; ++p) P[p] = Lk[P[p]] >= Lk[p] ? n : P[p];
   ++n;
 }
 
@@ -93,8 +107,10 @@ int famsa_slink_create(const uint32_t* lengths, uint32_t k, famsa_slink_t** out)
     s->k = k;
     s->len.assign(lengths, lengths + k);
     s->pi.assign(k, 0);
-    s->lambda.assign(k, Sim{-1, 1});
-    s->M.assign(k, Sim{-1, 1});
+    s->lk.assign(k, 0);
+    s->mk.assign(k, 0);
+    s->lv.assign(k, 0);
+    s->mv.assign(k, 0);
   } catch (...) {
     delete s;
     return famsa::set_error(FAMSA_LCS_ENOMEM, "out of host memory");
@@ -127,8 +143,9 @@ int famsa_slink_result(const famsa_slink_t* s, uint32_t* pi, int64_t* num, int64
     const uint32_t i = s->k - 1 - p;
     if (pi) pi[i] = s->k - 1 - s->pi[p];
     const bool root = s->pi[p] == p;
-    if (num) num[i] = root ? -1 : s->lambda[p].num;
-    if (den) den[i] = root ? 0 : s->lambda[p].den;
+    const int64_t L = (int64_t)(s->lv[p] & 0xFFFFFFFFu), d = (int64_t)(s->lv[p] >> 32);
+    if (num) num[i] = root ? -1 : L;
+    if (den) den[i] = root ? 0 : d * d;
   }
   return 0;
 }
