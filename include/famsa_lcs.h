@@ -198,8 +198,9 @@ int famsa_lcs_get_stats(const famsa_lcs_plan_t* plan, famsa_lcs_stats* stats);
  * Points are inserted from k-1 down to 0, so the consumer needs the tiles of
  * one family in descending order (FAMSA_LCS_DESCENDING); it keeps the
  * pointer representation pi(i) (the later point i joins) and lambda(i) (the
- * similarity at which it joins) as exact rationals L/indel^2, compared by
- * 64-bit cross-multiplication (exact for lengths up to FAMSA_LCS_MAX_LEN).
+ * similarity at which it joins) as exact rationals L/indel^2, ordered by the
+ * correctly rounded double of the ratio (exact for lengths up to
+ * FAMSA_LCS_MAX_LEN: different ratios never round to the same double).
  * ------------------------------------------------------------------------ */
 typedef struct famsa_slink_s famsa_slink_t;
 
