@@ -290,8 +290,9 @@ def main():
         print(json.dumps({"copy_bytes": x.numel() * 4}))
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the stage on a single MI355X "
-              "(the multi-GPU sharding is a design, not a run); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the stage runs on a single MI355X here "
+              "(sharding across GPUs is a design whose forest merge is tested on one GPU); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     from paper_1603_06958_amd import inputs
     import torch
