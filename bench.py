@@ -56,7 +56,8 @@ PEAK_INT_OPS = 256 * 128 * 2.4e9
 OPS_PER_CELL = 3.0 / 32.0             # AND + ADDC + BITOP3 per 32-cell dword-step
 STEP_VALUES = 1 << 28                 # int32 results per launch step (1 GiB per buffer)
 TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "lcs_fast_c4_hbm_traffic.txt")
-KERNEL_SOURCE = os.path.join(HERE, "paper_1603_06958_amd", "csrc", "lcs_kernels.hip")
+# the kernels and the constants that shape them (class bounds, LDS layout)
+KERNEL_SOURCES = [os.path.join(HERE, "paper_1603_06958_amd", "csrc", f) for f in ("lcs_kernels.hip", "lcs_common.h")]
 
 
 def _oracle_worker(args):
@@ -218,7 +219,7 @@ def traffic_per_launch(kernel):
     import hashlib
     try:
         text = open(TRAFFIC_SUMMARY).read()
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
     except OSError:
         return None, "no counter summary"
     if f"sha256[:16] = {sha}" not in text:

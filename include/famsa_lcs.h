@@ -176,7 +176,7 @@ int famsa_lcs_plan_dry_run(const uint8_t* codes, const uint64_t* seq_off, uint32
  * streams.  Per-kernel times are recorded only for plans that launch without
  * a graph (FAMSA_LCS_NO_GRAPH or FAMSA_LCS_PLAIN); step_ms is always there. */
 typedef struct famsa_lcs_stats {
-  double kernel_ms[5];     /* summed duration per kernel: [0] rows of <= 256 residues, [1] <= 512, [2] <= 896
+  double kernel_ms[5];     /* summed duration per kernel: [0] rows of <= 256 residues, [1] <= 384, [2] <= 896
                               (<= 512 with more than 20 symbols), [3] longer rows, in segments,
                               [4] plain one-pair-per-lane baseline (FAMSA_LCS_PLAIN) */
   uint64_t launches[5];

@@ -34,7 +34,7 @@ namespace famsa {
 
 constexpr int kLanes = 64;        // wavefront size on gfx950
 constexpr int kNumClasses = 5;    // 0..2 fast kernels by row length, 3 segmented long-row kernel, 4 plain kernel
-constexpr int kClassQMax[3] = {2, 4, 7};   // 128-bit mask quads per lane covered by classes 0..2 (W <= 8, 16, 28)
+constexpr int kClassQMax[3] = {2, 3, 7};   // 128-bit mask quads per lane covered by classes 0..2 (W <= 8, 12, 28)
 constexpr int kSeqAlign = 32;     // device code padding / alignment (bytes)
 constexpr size_t kMaxLds = 163840;  // LDS bytes per workgroup on gfx950 (capped by the device's own limit)
 extern size_t g_max_lds;          // min(kMaxLds, device limit), set when a plan or server opens a device
