@@ -46,18 +46,21 @@ struct GroupDesc {          // 32 bytes
   uint32_t nrows;           // rows in this group (1..64)
   uint32_t W;               // dwords per lane = ceil(max row length / 32), >= 1
   uint32_t fam_base;        // global sequence index of the family's first member
-  uint32_t colmap_base;     // column position -> family-local index via colmap[colmap_base + c];
-                            //   kNoMap: positions are the indices themselves
-  uint32_t rowbase_base;    // family-local index -> step offset of its row via rowbase[rowbase_base + j];
-                            //   kNoMap: every column index is above every lane row (tile mode)
-  uint32_t pad0, pad1;
+  uint32_t colmap_base;     // kNoMap: column positions are the family-local indices themselves.
+                            //   Otherwise positions c < nmap are mapped, index colmap[colmap_base + c],
+                            //   and positions c >= nmap are the indices c + shift
+  uint32_t rowbase_base;    // mapped position c -> step offset of that column's own row,
+                            //   rowbase[rowbase_base + c] (kNoMap with colmap_base)
+  uint32_t nmap;            // mapped positions
+  uint32_t shift;           // index of an unmapped position c is c + shift
 };
 constexpr uint32_t kNoMap = 0xFFFFFFFFu;
 
 // A lane's row.  Columns are walked by position c; the lane needs column c
-// iff c > pos.  Its result for column index b goes to
+// iff c > pos.  Its result for column index b at position c goes to
 //   out_off + (b - orig - 1)            if orig < b  (this row's own tile row)
-//   rowbase[b] + (orig - b - 1)         otherwise    (row b holds the pair)
+//   rowbase[c] + (orig - b - 1)         otherwise    (row b holds the pair;
+//                                                     only mapped positions)
 struct LaneDesc {           // 24 bytes
   uint64_t out_off;         // step-buffer offset of LCS(orig, orig + 1)
   uint32_t seq;             // global sequence index
@@ -81,7 +84,7 @@ struct PlainRow {           // 48 bytes
   uint32_t seq, pos, orig;
   uint32_t fam_base;
   uint32_t ncols;           // column positions run over [0, ncols)
-  uint32_t colmap_base, rowbase_base;
+  uint32_t colmap_base, rowbase_base;  // as GroupDesc, every position mapped
   uint32_t pad;
 };
 

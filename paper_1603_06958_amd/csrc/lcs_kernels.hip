@@ -151,8 +151,16 @@ __device__ __forceinline__ void run_item(const DeviceBatch& bt, const uint32_t* 
     if (lane == 0) col = atomicAdd(s_col, 1u);
     col = __builtin_amdgcn_readfirstlane(col);
     if (col >= c1) break;
-    const uint32_t b = g.colmap_base == kNoMap ? col : colmap[g.colmap_base + col];
-    const uint64_t rb = g.rowbase_base == kNoMap ? 0ull : rowbase[g.rowbase_base + b];
+    uint32_t b = col;
+    uint64_t rb = 0;
+    if (g.colmap_base != kNoMap) {
+      if (col < g.nmap) {
+        b = colmap[g.colmap_base + col];
+        rb = rowbase[g.rowbase_base + col];
+      } else {
+        b = col + g.shift;  // above every row of the group
+      }
+    }
     const uint32_t s = g.fam_base + b;
     const uint32_t n = bt.len[s];
     const uint4* B = reinterpret_cast<const uint4*>(bt.sym + bt.sym_off[s]) + vzero;
@@ -402,8 +410,15 @@ __global__ __launch_bounds__(1024) void lcs_long_kernel(
       uint64_t rb = 0;
       const uint4* B = nullptr;
       if (valid) {
-        b = g.colmap_base == kNoMap ? col : colmap[g.colmap_base + col];
-        rb = g.rowbase_base == kNoMap ? 0ull : rowbase[g.rowbase_base + b];
+        b = col;
+        if (g.colmap_base != kNoMap) {
+          if (col < g.nmap) {
+            b = colmap[g.colmap_base + col];
+            rb = rowbase[g.rowbase_base + col];
+          } else {
+            b = col + g.shift;
+          }
+        }
         const uint32_t s = g.fam_base + b;
         n = bt.len[s];
         B = reinterpret_cast<const uint4*>(bt.sym + bt.sym_off[s]);
@@ -515,7 +530,7 @@ __global__ __launch_bounds__(256) void lcs_plain_kernel(
       for (uint32_t w = 0; w < Wd; ++w) cnt += __builtin_popcountll(~V[(uint64_t)w * nthreads]);
     }
     const uint64_t o = row.orig < b ? row.out_off + (b - row.orig - 1u)
-                                    : rowbase[row.rowbase_base + b] + (row.orig - b - 1u);
+                                    : rowbase[row.rowbase_base + col] + (row.orig - b - 1u);
     out[o] = tile_value(values, cnt, m, n);
   }
 }

@@ -274,16 +274,17 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
     const uint32_t fb = sf.fam.fam_base, k = sf.fam.k;
     if (k < 2) continue;
     if (sf.whole && !plain_only) {
-      const uint32_t rb_base = (uint32_t)wl.rowbase.size();
-      wl.rowbase.resize(rb_base + k, 0);
+      std::vector<uint64_t> rowoff(k, 0);  // step offset of (i, i+1), by row
       for (const TileWork& t : sf.tiles)
-        for (uint32_t i = t.r0; i < t.r1; ++i) wl.rowbase[rb_base + i] = t.out_off + tri_rows(k, t.r0, i);
+        for (uint32_t i = t.r0; i < t.r1; ++i) rowoff[i] = t.out_off + tri_rows(k, t.r0, i);
       std::vector<uint32_t> perm(k);
       std::iota(perm.begin(), perm.end(), 0u);
       std::stable_sort(perm.begin(), perm.end(),
                        [&](uint32_t a, uint32_t b) { return len[fb + a] > len[fb + b]; });
       const uint32_t cm_base = (uint32_t)wl.colmap.size();
       wl.colmap.insert(wl.colmap.end(), perm.begin(), perm.end());
+      const uint32_t rb_base = (uint32_t)wl.rowbase.size();
+      for (uint32_t q = 0; q < k; ++q) wl.rowbase.push_back(rowoff[perm[q]]);
       colprefs.emplace_back(k + 1, 0);
       std::vector<uint64_t>& cp = colprefs.back();
       for (uint32_t q = 0; q < k; ++q) cp[q + 1] = cp[q] + len[fb + perm[q]];
@@ -297,10 +298,12 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
         g.fam_base = fb;
         g.colmap_base = cm_base;
         g.rowbase_base = rb_base;
+        g.nmap = k;
+        g.shift = 0;
         const int cls = class_of(W, sigma);
         for (uint32_t l = 0; l < nrows; ++l) {
           const uint32_t a = perm[P + l];
-          LaneDesc ld{wl.rowbase[rb_base + a], fb + a, P + l, a, 0};
+          LaneDesc ld{rowoff[a], fb + a, P + l, a, 0};
           wl.cells[cls] += (uint64_t)len[fb + a] * (cp[k] - cp[P + l + 1]);
           wl.lanes.push_back(ld);
         }
@@ -313,16 +316,69 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
       // and sorted by length so each group's rows have similar lengths
       std::vector<uint32_t> rows;
       std::vector<uint64_t> rowoff;  // step offset of (i, i+1), by position in `rows`
-      for (const TileWork& t : sf.tiles)
+      uint32_t R0 = k, R1 = 0;
+      for (const TileWork& t : sf.tiles) {
         for (uint32_t i = t.r0; i < t.r1; ++i) {
           rows.push_back(i);
           rowoff.push_back(t.out_off + tri_rows(k, t.r0, i));
         }
+        R0 = std::min(R0, t.r0);
+        R1 = std::max(R1, t.r1);
+      }
       std::vector<uint32_t> ord(rows.size());
       std::iota(ord.begin(), ord.end(), 0u);
       if (!plain_only)
         std::stable_sort(ord.begin(), ord.end(),
                          [&](uint32_t a, uint32_t b) { return len[fb + rows[a]] > len[fb + rows[b]]; });
+      const uint32_t ns = (uint32_t)rows.size();
+      if (!plain_only && ns && R1 - R0 == ns) {
+        // The step's rows are one range [R0, R1).  Column positions: first
+        // those rows in the groups' (length) order, then the columns R1..k-1.
+        // A pair of two step rows is computed once, by the row that comes
+        // first in that order, as in family mode; every later column is
+        // above every step row.  A group then walks no column below its
+        // rows beyond its own 64 x 64 corner.
+        const uint32_t np = ns + (k - R1);
+        const uint32_t cm_base = (uint32_t)wl.colmap.size();
+        const uint32_t rb_base = (uint32_t)wl.rowbase.size();
+        colprefs.emplace_back(np + 1, 0);
+        std::vector<uint64_t>& cp = colprefs.back();
+        uint32_t colmax = 0;  // longest column (bounds the long-row kernel's carry rows)
+        for (uint32_t q = 0; q < np; ++q) {
+          const uint32_t j = q < ns ? rows[ord[q]] : R1 + (q - ns);
+          if (q < ns) {
+            wl.colmap.push_back(j);
+            wl.rowbase.push_back(rowoff[ord[q]]);
+          }
+          cp[q + 1] = cp[q] + len[fb + j];
+          colmax = std::max(colmax, len[fb + j]);
+        }
+        for (uint32_t P = 0; P < ns; P += kLanes) {
+          if (P + 1 >= np) continue;  // only the family's last row: no pairs
+          const uint32_t nrows = std::min<uint32_t>(kLanes, ns - P);
+          const uint32_t W = std::max<uint32_t>(1, (len[fb + rows[ord[P]]] + 31) / 32);
+          GroupDesc g{};
+          g.lane_first = (uint32_t)wl.lanes.size();
+          g.nrows = nrows;
+          g.W = W;
+          g.fam_base = fb;
+          g.colmap_base = cm_base;
+          g.rowbase_base = rb_base;
+          g.nmap = ns;
+          g.shift = R1 - ns;
+          const int cls = class_of(W, sigma);
+          for (uint32_t l = 0; l < nrows; ++l) {
+            const uint32_t i = rows[ord[P + l]];
+            LaneDesc ld{rowoff[ord[P + l]], fb + i, P + l, i, 0};
+            wl.cells[cls] += (uint64_t)len[fb + i] * (lenprefix[fb + k] - lenprefix[fb + i + 1]);
+            wl.lanes.push_back(ld);
+          }
+          if (cls == 3) wl.long_col_max = std::max(wl.long_col_max, colmax);
+          pend.push_back(PendingGroup{g, P + 1, np, cp.data(), 0});
+          span += np - (P + 1);
+        }
+        continue;
+      }
       for (size_t P = 0; P < ord.size(); P += kLanes) {
         const uint32_t nrows = (uint32_t)std::min<size_t>(kLanes, ord.size() - P);
         uint32_t maxlen = 0, mini = 0xFFFFFFFFu;

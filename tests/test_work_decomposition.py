@@ -26,6 +26,8 @@ CASES = {
     "sigma32": (lambda: inputs.random_family(50, 0, 900, 4, alphabet=32), dict(alphabet_size=32, tile_rows=9)),
     "small_cols": (lambda: inputs.random_family(300, 0, 500, 5), dict(tile_rows=64, step_values=9000,
                                                                       cols_per_item=16)),
+    "desc_steps": (lambda: inputs.random_family(300, 0, 500, 7), dict(tile_rows=20, step_values=9000,
+                                                                      flags=B.DESCENDING)),
 }
 
 
@@ -61,3 +63,25 @@ def test_multi_family_coverage_and_whole_families():
 def test_dry_run_validates():
     with pytest.raises(B.FamsaError):
         dry_run(inputs.from_sequences([np.array([25], np.uint8)]))
+
+
+@pytest.mark.parametrize("opt", [dict(tile_rows=20, step_values=9000), dict(tile_rows=20, step_values=9000,
+                                                                          flags=B.DESCENDING),
+                                 dict(tile_rows=7, step_values=3000, cols_per_item=16)])
+def test_tile_mode_walks_no_column_below_its_rows(opt):
+    # Several tiles per step: every group starts at the column position after
+    # its first row, its rows hold consecutive positions, and the only columns
+    # it walks without storing are those of its own 64 x 64 corner.
+    b = inputs.random_family(300, 0, 500, 8)
+    d, info = dry_run(b, **opt)
+    check_coverage(d)
+    assert len(d["steps"]) > 2 and (d["steps"]["tile_end"] - d["steps"]["tile_begin"]).max() > 1
+    G, L, I = d["groups"], d["lanes"], d["items"]
+    first_c0 = {}
+    for it in I:
+        first_c0[int(it["group"])] = min(first_c0.get(int(it["group"]), 1 << 32), int(it["c0"]))
+    for gi, g in enumerate(G):
+        assert g["colmap_base"] != 0xFFFFFFFF  # the step's rows are one range: columns are mapped
+        pos = L[g["lane_first"]:g["lane_first"] + g["nrows"]]["pos"].astype(np.int64)
+        assert np.array_equal(pos, pos[0] + np.arange(g["nrows"]))
+        assert first_c0[gi] == pos[0] + 1

@@ -16,7 +16,7 @@ DT = {
     "steps": np.dtype([("tile_begin", "<u8"), ("tile_end", "<u8"), ("values", "<u8")]),
     "ranges": np.dtype([("begin", "<u4", 5), ("end", "<u4", 5), ("plain_pairs", "<u8")]),
     "groups": np.dtype([("lane_first", "<u4"), ("nrows", "<u4"), ("W", "<u4"), ("fam_base", "<u4"),
-                        ("colmap_base", "<u4"), ("rowbase_base", "<u4"), ("pad0", "<u4"), ("pad1", "<u4")]),
+                        ("colmap_base", "<u4"), ("rowbase_base", "<u4"), ("nmap", "<u4"), ("shift", "<u4")]),
     "lanes": np.dtype([("out_off", "<u8"), ("seq", "<u4"), ("pos", "<u4"), ("orig", "<u4"), ("pad", "<u4")]),
     "items": np.dtype([("group", "<u4"), ("c0", "<u4"), ("c1", "<u4"), ("pad", "<u4")]),
     "prows": np.dtype([("out_off", "<u8"), ("pair_first", "<u8"), ("seq", "<u4"), ("pos", "<u4"), ("orig", "<u4"),
@@ -70,7 +70,12 @@ def emulate_step(d, s):
             g = d["groups"][it["group"]]
             ln = d["lanes"][g["lane_first"]:g["lane_first"] + g["nrows"]]
             cols = np.arange(it["c0"], it["c1"], dtype=np.int64)
-            b = cols if g["colmap_base"] == NOMAP else colmap[g["colmap_base"] + cols].astype(np.int64)
+            if g["colmap_base"] == NOMAP:
+                b = cols
+            else:  # mapped positions first, then c + shift
+                mapped = cols < g["nmap"]
+                b = np.where(mapped, colmap[g["colmap_base"] + np.minimum(cols, int(g["nmap"]) - 1)].astype(np.int64),
+                             cols + int(g["shift"]))
             for lane in ln:
                 m = cols > lane["pos"]
                 bb = b[m]
@@ -79,7 +84,10 @@ def emulate_step(d, s):
                     assert (bb > orig).all()
                     o = int(lane["out_off"]) + (bb - orig - 1)
                 else:
-                    rb = rowbase[g["rowbase_base"] + bb].astype(np.int64)
+                    cc = cols[m]
+                    below = bb < orig
+                    assert (cc[below] < g["nmap"]).all(), "a column below the row must be mapped"
+                    rb = rowbase[g["rowbase_base"] + np.minimum(cc, int(g["nmap"]) - 1)].astype(np.int64)
                     o = np.where(orig < bb, int(lane["out_off"]) + (bb - orig - 1), rb + (orig - bb - 1))
                 offs.append(o)
                 gi.append(np.full(bb.size, int(g["fam_base"]) + orig))
@@ -96,7 +104,7 @@ def emulate_step(d, s):
         b = np.where(row["colmap_base"] == NOMAP, col,
                      cm[np.where(row["colmap_base"] == NOMAP, 0, row["colmap_base"].astype(np.int64) + col)])
         orig = row["orig"].astype(np.int64)
-        rbi = np.where(row["rowbase_base"] == NOMAP, 0, row["rowbase_base"].astype(np.int64) + b)
+        rbi = np.where(row["rowbase_base"] == NOMAP, 0, row["rowbase_base"].astype(np.int64) + col)
         rbs = rowbase if rowbase.size else np.zeros(1, np.uint64)
         rb = rbs[rbi].astype(np.int64)
         o = np.where(orig < b, row["out_off"].astype(np.int64) + (b - orig - 1), rb + (orig - b - 1))
