@@ -30,7 +30,9 @@ the kernel's own.  Also reported, in the same JSON line:
   row decoded to host memory);
 * cpu_baseline: the CPU oracle (plain DP) on a bounded sample of the same
   workload's pairs, on the host's cores;
-* c3: batched (persistent, graph-replayed) vs plain per-family launches;
+* c3: batched (persistent, graph-replayed) vs plain (one launch per tile,
+  each waiting for the previous tile's delivery) and plain_async (the same
+  launches without the waits); median of 5 passes each;
 * serve: continuous-batching jobs, pairs/s and p50/p99 latency.
 """
 from __future__ import annotations
@@ -233,13 +235,13 @@ def traffic_per_launch(kernel):
     return None, "kernel not in the counter summary"
 
 
-def run_c3(steps=1):
+def run_c3(passes=5):
     from paper_1603_06958_amd import binding as B, inputs
     b = inputs.c3()
     out = {"workload": "c3: 64 tree-evolved families, k log-uniform [50,5000], root length log-uniform [30,2000]",
            "pairs": b.pairs(), "cells": b.cells()}
     res = {}
-    for name, flags in [("batched", 0), ("plain", B.PLAIN)]:
+    for name, flags in [("batched", 0), ("plain", B.PLAIN), ("plain_async", B.PLAIN | B.PLAIN_ASYNC)]:
         p = B.Plan.from_batch(b, flags=flags)
         chk = [0]
 
@@ -248,17 +250,19 @@ def run_c3(steps=1):
             return 0
 
         p.run(fn)  # warm-up
-        best = None
-        for _ in range(steps):
+        times = []
+        for _ in range(passes):
             t0 = time.perf_counter()
             p.run(fn)
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        res[name] = best
-        out[f"{name}_s"] = round(best, 4)
-        out[f"{name}_gcups"] = round(b.cells() / best / 1e9, 1)
+            times.append(time.perf_counter() - t0)
+        med = float(np.median(times))
+        res[name] = med
+        out[f"{name}_s"] = round(med, 4)
+        out[f"{name}_gcups"] = round(b.cells() / med / 1e9, 1)
         p.close()
+    out["passes"] = passes
     out["batched_over_plain"] = round(res["plain"] / res["batched"], 2)
+    out["batched_over_plain_async"] = round(res["plain_async"] / res["batched"], 2)
     return out
 
 

@@ -68,6 +68,9 @@ typedef enum famsa_lcs_status {
 #define FAMSA_LCS_OUT_SIM      0x80u /* tiles hold the similarity LCS / indel^2 as float32 (the float rounding
                                         of the correctly rounded double; +infinity when indel = 0) instead of
                                         LCS (Methods, "Pairwise similarities calculation"); excludes OUT_INDEL */
+#define FAMSA_LCS_PLAIN_ASYNC  0x100u /* with FAMSA_LCS_PLAIN only: two output buffers on one compute stream, and
+                                         each tile's launch is issued without waiting for the previous tile's
+                                         delivery (the plain kernels with no host synchronisation between them) */
 
 /* What a tile's values are (famsa_lcs_tile.values). */
 #define FAMSA_LCS_VALUES_LCS   0u
@@ -84,6 +87,9 @@ typedef struct famsa_lcs_options {
   uint32_t flags;          /* FAMSA_LCS_* flags above */
   uint32_t cols_per_item;  /* columns per work item, 0 = tuned/default */
   uint64_t step_values;    /* int32 values per launch step (several tiles), 0 = default (2^27) */
+  uint64_t step_cells;     /* server only: cells |A||B| per scheduler step, which bounds how long a
+                              step runs and so how long a new job waits; a step still takes at
+                              least one tile; 0 = no bound (plans ignore it) */
 } famsa_lcs_options;
 
 /* Fill *opt with the defaults above. */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfamsa_lcs.so")
 OK, EINVAL, ENOMEM, EDEVICE, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5
 PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE, ONE_STREAM = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 OUT_INDEL, OUT_SIM = 0x40, 0x80
+PLAIN_ASYNC = 0x100
 VALUES_LCS, VALUES_INDEL, VALUES_SIM = 0, 1, 2
 MAX_LEN = 65535
 
@@ -35,7 +36,7 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("alphabet_size", ctypes.c_uint32),
                 ("tile_rows", ctypes.c_uint32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("hbm_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("cols_per_item", ctypes.c_uint32),
-                ("step_values", ctypes.c_uint64)]
+                ("step_values", ctypes.c_uint64), ("step_cells", ctypes.c_uint64)]
 
 
 class Tile(ctypes.Structure):
@@ -166,7 +167,8 @@ def check(rc: int):
 
 
 def make_options(alphabet_size: int = 20, tile_rows: int = 1024, device: int = 0, stream: Optional[int] = None,
-                 hbm_budget: int = 0, flags: int = 0, cols_per_item: int = 0, step_values: int = 0) -> Options:
+                 hbm_budget: int = 0, flags: int = 0, cols_per_item: int = 0, step_values: int = 0,
+                 step_cells: int = 0) -> Options:
     o = Options()
     lib().famsa_lcs_default_options(ctypes.byref(o))
     o.alphabet_size = alphabet_size
@@ -177,6 +179,7 @@ def make_options(alphabet_size: int = 20, tile_rows: int = 1024, device: int = 0
     o.flags = flags
     o.cols_per_item = cols_per_item
     o.step_values = step_values
+    o.step_cells = step_cells
     return o
 
 

@@ -63,8 +63,14 @@ struct famsa_lcs_plan_s {
   }
   StepCtl* ctl(int slot) const { return d_ctl.as<StepCtl>() + slot; }
   bool plain() const { return opt.flags & FAMSA_LCS_PLAIN; }
-  // compute stream of a buffer slot: both slots share stream 0 under ONE_STREAM
-  hipStream_t cstream(int slot) const { return (opt.flags & FAMSA_LCS_ONE_STREAM) ? cs[0] : cs[slot]; }
+  // output buffer slots: the plain baseline has one (each launch waits for
+  // the previous tile's delivery) unless FAMSA_LCS_PLAIN_ASYNC asks for two
+  int slots() const { return plain() && !(opt.flags & FAMSA_LCS_PLAIN_ASYNC) ? 1 : 2; }
+  // compute stream of a buffer slot: both slots share stream 0 under
+  // ONE_STREAM and in the plain baseline
+  hipStream_t cstream(int slot) const {
+    return (opt.flags & (FAMSA_LCS_ONE_STREAM | FAMSA_LCS_PLAIN)) ? cs[0] : cs[slot];
+  }
   // Steps replay captured graphs unless FAMSA_LCS_NO_GRAPH asks for direct
   // launches (which are timed per kernel class with events).
   bool use_graph() const { return !(opt.flags & (FAMSA_LCS_NO_GRAPH | FAMSA_LCS_PLAIN)); }
@@ -389,7 +395,7 @@ int famsa_lcs_plan_s::run(uint64_t first_tile, famsa_lcs_tile_fn fn, void* user)
   const uint64_t s0 = tiles[first_tile].step, ns = steps.size();
   const bool dev_tiles = opt.flags & FAMSA_LCS_DEVICE_TILES;
   const bool timed = !use_graph();
-  const int nslots = plain() ? 1 : 2;
+  const int nslots = slots();
   FAMSA_HIP(hipSetDevice(opt.device));
   // the first step each control block computes, and its stride
   // step s runs on slot s % nslots: seed each slot's control block with the
@@ -500,6 +506,7 @@ void famsa_lcs_default_options(famsa_lcs_options* o) {
   o->flags = 0;
   o->cols_per_item = 0;
   o->step_values = 0;
+  o->step_cells = 0;
 }
 
 const char* famsa_lcs_last_error(void) { return last_error_text(); }
@@ -556,7 +563,7 @@ int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
   if ((rc = p->d_ctl.alloc(2 * sizeof(StepCtl)))) return fail(rc);
   uint64_t step_max = 0;
   for (const auto& st : p->steps) step_max = std::max(step_max, st.values);
-  const int nbuf = p->plain() ? 1 : 2;
+  const int nbuf = p->slots();
   for (int i = 0; i < nbuf; ++i) {
     if ((rc = p->d_out[i].alloc(std::max<uint64_t>(step_max, 1) * 4))) return fail(rc);
     if (!(o.flags & FAMSA_LCS_DEVICE_TILES) && (rc = p->h_out[i].alloc(std::max<uint64_t>(step_max, 1) * 4)))

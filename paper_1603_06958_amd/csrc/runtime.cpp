@@ -84,10 +84,13 @@ int normalize_options(const famsa_lcs_options* in, Opts* o) {
   if (d.tile_rows < 1) return set_error(FAMSA_LCS_EINVAL, "tile_rows must be >= 1");
   if (d.device < 0) return set_error(FAMSA_LCS_EINVAL, "device %d < 0", d.device);
   const uint32_t known = FAMSA_LCS_PLAIN | FAMSA_LCS_DESCENDING | FAMSA_LCS_DEVICE_TILES | FAMSA_LCS_NO_GRAPH |
-                         FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM | FAMSA_LCS_OUT_INDEL | FAMSA_LCS_OUT_SIM;
+                         FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM | FAMSA_LCS_OUT_INDEL | FAMSA_LCS_OUT_SIM |
+                         FAMSA_LCS_PLAIN_ASYNC;
   if (d.flags & ~known) return set_error(FAMSA_LCS_EINVAL, "unknown flag bits 0x%x", d.flags & ~known);
   if ((d.flags & FAMSA_LCS_OUT_INDEL) && (d.flags & FAMSA_LCS_OUT_SIM))
     return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_OUT_INDEL and FAMSA_LCS_OUT_SIM exclude each other");
+  if ((d.flags & FAMSA_LCS_PLAIN_ASYNC) && !(d.flags & FAMSA_LCS_PLAIN))
+    return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_PLAIN_ASYNC needs FAMSA_LCS_PLAIN");
   if (d.cols_per_item > (1u << 20)) return set_error(FAMSA_LCS_EINVAL, "cols_per_item %u too large", d.cols_per_item);
   o->sigma = d.alphabet_size;
   o->tile_rows = d.tile_rows;
@@ -97,6 +100,7 @@ int normalize_options(const famsa_lcs_options* in, Opts* o) {
   o->flags = d.flags;
   o->cols_per_item = d.cols_per_item;
   o->step_values = d.step_values ? d.step_values : (1ull << 27);
+  o->step_cells = d.step_cells;
   return 0;
 }
 

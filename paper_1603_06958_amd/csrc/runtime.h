@@ -64,6 +64,7 @@ struct Opts {
   uint32_t flags = 0;
   uint32_t cols_per_item = 0;
   uint64_t step_values = 0;
+  uint64_t step_cells = 0;
 };
 int normalize_options(const famsa_lcs_options* in, Opts* out);
 

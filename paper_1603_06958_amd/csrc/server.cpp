@@ -85,6 +85,7 @@ struct famsa_lcs_server_s {
   LaunchParams lp;
   uint64_t budget = 0, fixed = 0, in_use = 0, peak = 0;
   uint64_t step_values = 0;
+  uint64_t step_cells = 0;  // 0: steps bounded by values only
   std::map<uint32_t, std::unique_ptr<Job>> jobs;
   std::deque<Job*> queue;
   std::vector<Job*> active;
@@ -141,19 +142,33 @@ int famsa_lcs_server_s::compose(Slot& sl, Staging& st) {
   st.symoff.clear();
   st.len.clear();
   std::vector<uint64_t> lenprefix(1, 0);
+  uint64_t cells = 0;  // of the tiles taken so far
+  // a step that is still empty takes the next unit whatever its size
+  auto fits = [&](uint64_t v, uint64_t c) {
+    return sl.values == 0 || (sl.values + v <= step_values && (!step_cells || cells + c <= step_cells));
+  };
   for (Job* j : cand) {
     const uint32_t first = j->next_tile;
     uint32_t last = first;  // tiles [first, last) go in this step
-    uint64_t vals = 0;
+    uint64_t vals = 0, jc = 0;
     if (j->whole) {
-      for (uint32_t t = first; t < j->tiles.size(); ++t) vals += j->tiles[t].count;
-      if (sl.values && sl.values + vals > step_values) continue;
+      for (uint32_t t = first; t < j->tiles.size(); ++t) {
+        vals += j->tiles[t].count;
+        jc += j->tile_cells[t];
+      }
+      if (!fits(vals, jc)) continue;
       last = (uint32_t)j->tiles.size();
     } else {
-      while (last < j->tiles.size() && (sl.values + vals == 0 || sl.values + vals + j->tiles[last].count <= step_values))
-        vals += j->tiles[last++].count;
+      while (last < j->tiles.size() &&
+             ((vals == 0 && fits(j->tiles[last].count, j->tile_cells[last])) ||
+              (vals && sl.values + vals + j->tiles[last].count <= step_values &&
+               (!step_cells || cells + jc + j->tile_cells[last] <= step_cells)))) {
+        vals += j->tiles[last].count;
+        jc += j->tile_cells[last++];
+      }
     }
     if (last == first) continue;
+    cells += jc;
     StepFamily sf;
     sf.fam = FamilyRef{(uint32_t)st.len.size(), j->k};
     sf.whole = j->whole;
@@ -175,7 +190,7 @@ int famsa_lcs_server_s::compose(Slot& sl, Staging& st) {
     }
     j->next_tile = last;
     fams.push_back(std::move(sf));
-    if (sl.values >= step_values) break;
+    if (sl.values >= step_values || (step_cells && cells >= step_cells)) break;
   }
   st.wl = WorkLists();
   if (!fams.empty()) build_step(st.wl, fams, st.len, lenprefix, opt.sigma, lp, false);
@@ -287,6 +302,7 @@ int famsa_lcs_server_create(const famsa_lcs_options* opt, famsa_lcs_server_t** o
   FAMSA_HIP(hipMemGetInfo(&freeb, &totalb));
   s->budget = o.hbm_budget ? o.hbm_budget : (uint64_t)(freeb * 0.9);
   s->step_values = o.step_values;
+  s->step_cells = o.step_cells;
   s->fixed = 2 * s->step_values * 4 + (64u << 20);  // step buffers + descriptor headroom
   if (s->fixed >= s->budget) {
     s->step_values = std::max<uint64_t>(1024, (s->budget / 4) / 8);
@@ -368,9 +384,6 @@ int famsa_lcs_server_step(famsa_lcs_server_t* s, famsa_lcs_tile_fn fn, void* use
   const bool issued = s->slot[cur].busy;
   rc = s->deliver(prev, fn, user);
   if (issued) s->step_no++;
-  if (!issued && !s->slot[prev].busy && !s->active.empty()) {
-    // nothing was in flight and nothing issued: deliver happened above; try once more
-  }
   if (active) *active = (uint32_t)(s->active.size() + s->queue.size());
   return rc;
 }

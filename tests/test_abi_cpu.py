@@ -75,11 +75,29 @@ def test_einval_families():
     assert plan_rc(c, off, fam=[0, 3, 2, 4], nfam=3)[0] == B.EINVAL  # decreasing
 
 
+def test_options_layout_and_older_callers():
+    # the Python mirror has the C layout, and a caller built before the last
+    # field (step_cells) was added still gets a plan-time answer, not EINVAL
+    o = B.make_options()
+    assert o.struct_size == ctypes.sizeof(B.Options)
+    o.struct_size = B.Options.step_cells.offset
+    h = ctypes.c_void_p()
+    off = np.array([0, 1], np.uint64)
+    c = np.zeros(1, np.uint8)
+    info = B.PlanInfo()
+    rc = B.lib().famsa_lcs_plan_dry_run(c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                       off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 1, None, 0,
+                                       ctypes.byref(o), None, ctypes.byref(info))
+    assert rc == 0, B.last_error()
+
+
 def test_einval_options():
     assert plan_rc([0], [0, 1], tile_rows=0)[0] == B.EINVAL
-    assert plan_rc([0], [0, 1], flags=0x100)[0] == B.EINVAL
+    assert plan_rc([0], [0, 1], flags=0x200)[0] == B.EINVAL
     rc, msg = plan_rc([0], [0, 1], flags=B.OUT_INDEL | B.OUT_SIM)
     assert rc == B.EINVAL and "exclude" in msg
+    rc, msg = plan_rc([0], [0, 1], flags=B.PLAIN_ASYNC)
+    assert rc == B.EINVAL and "needs FAMSA_LCS_PLAIN" in msg
     L = B.lib()
     o = B.make_options()
     o.struct_size = 4

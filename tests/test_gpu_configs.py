@@ -57,7 +57,7 @@ def test_c4_sampled_two_streams_with_graphs():
 
 def test_c5_jobs_sampled_in_the_serving_configuration():
     # every job of the serving workload through the server as bench.py runs
-    # it (2^24-value steps, 512-row tiles), arrivals replayed at once
+    # it (2^24-value, 2^41-cell steps, 256-row tiles), arrivals replayed at once
     from paper_1603_06958_amd import serve
     jobs = inputs.c5(seed=4, njobs=40, rate_per_s=serve.C5_RATE_PER_S)  # the bench's 40 jobs
     samplers = {}
@@ -70,7 +70,8 @@ def test_c5_jobs_sampled_in_the_serving_configuration():
         samplers[jid](local)
 
     r_ids = {}
-    srv = serve.Server(step_values=serve.SERVE_STEP_VALUES, tile_rows=serve.SERVE_TILE_ROWS)
+    srv = serve.Server(step_values=serve.SERVE_STEP_VALUES, step_cells=serve.SERVE_STEP_CELLS,
+                       tile_rows=serve.SERVE_TILE_ROWS)
     for i, j in enumerate(jobs):
         r_ids[srv.submit(j.batch.codes, j.batch.seq_off)] = i
     active = 1

@@ -29,7 +29,8 @@ def test_c1_full():
     check_all_tiles(b, tiles, 1024)
 
 
-@pytest.mark.parametrize("flags", [B.NO_GRAPH, B.PLAIN, B.DESCENDING, B.NO_GRAPH | B.DESCENDING])
+@pytest.mark.parametrize("flags", [B.NO_GRAPH, B.PLAIN, B.PLAIN | B.PLAIN_ASYNC, B.DESCENDING,
+                                   B.NO_GRAPH | B.DESCENDING])
 def test_c1_modes(flags):
     b = inputs.c1()
     tiles, _, _ = run(b, flags=flags, tile_rows=37)
@@ -82,10 +83,11 @@ def test_multi_family_uneven():
     tiles, info, _ = run(b, tile_rows=50)
     assert info.nfam == 10
     check_all_tiles(b, tiles, 50)
-    tiles2, _, _ = run(b, tile_rows=50, flags=B.PLAIN)
-    assert tiles2.keys() == tiles.keys()
-    for key in tiles:
-        assert np.array_equal(tiles[key], tiles2[key])
+    for flags in (B.PLAIN, B.PLAIN | B.PLAIN_ASYNC):
+        tiles2, _, _ = run(b, tile_rows=50, flags=flags)
+        assert tiles2.keys() == tiles.keys()
+        for key in tiles:
+            assert np.array_equal(tiles[key], tiles2[key])
 
 
 @pytest.mark.parametrize("sigma", [1, 2, 32])

@@ -33,10 +33,10 @@ def collect(jobs, **opt):
     return got, r
 
 
-@pytest.mark.parametrize("R,step_values", [(64, 0), (16, 5000)])
-def test_serving_matches_oracle_and_alone(R, step_values):
+@pytest.mark.parametrize("R,step_values,step_cells", [(64, 0, 0), (16, 5000, 0), (32, 0, 3_000_000)])
+def test_serving_matches_oracle_and_alone(R, step_values, step_cells):
     jobs = small_jobs()
-    got, r = collect(jobs, tile_rows=R, step_values=step_values)
+    got, r = collect(jobs, tile_rows=R, step_values=step_values, step_cells=step_cells)
     ids = r["job_ids"]
     for jid, i in ids.items():
         b = jobs[i].batch
@@ -70,3 +70,11 @@ def test_job_too_large_is_refused():
         srv.submit(b.codes, b.seq_off)
     assert e.value.code == B.ENOMEM
     srv.close()
+
+
+def test_alone_service_times():
+    # each job alone on an idle server, one after the other: the server is
+    # idle again after each, so every job gets a positive, finite time
+    jobs = small_jobs(4, seed=8)
+    t = serve.alone_ms(jobs, tile_rows=64)
+    assert t.shape == (4,) and (t > 0).all() and np.isfinite(t).all()
