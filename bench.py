@@ -29,7 +29,8 @@ the kernel's own.  Also reported, in the same JSON line:
   (one profile-wide round of gap runs inserted into every sequence, every
   row decoded to host memory);
 * cpu_baseline: the CPU oracle (plain DP) on a bounded sample of the same
-  workload's pairs, on the host's cores;
+  workload's pairs, on the host's cores, and its single-thread rate on 10^4
+  of those pairs and on every pair of c1;
 * c3: batched (persistent, graph-replayed) vs plain (one launch per tile,
   each waiting for the previous tile's delivery) and plain_async (the same
   launches without the waits); median of 5 passes each;
@@ -102,9 +103,22 @@ def cpu_baseline(b, seconds_target=12.0, seed=7):
     with mp.get_context("fork").Pool(cores) as pool:
         pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
+    # one thread: 10^4 seeded pairs of the workload, and every pair of c1
+    from paper_1603_06958_amd import inputs
+    a = rng.integers(0, k, 10000)
+    c = rng.integers(0, k, 10000)
+    t0 = time.perf_counter()
+    oracle.lcs_pairs(b.codes, b.seq_off, a, c)
+    st_sample = float((L[a] * L[c]).sum()) / (time.perf_counter() - t0) / 1e9
+    c1 = inputs.c1()
+    i1, j1 = np.triu_indices(c1.nseq, 1)
+    t0 = time.perf_counter()
+    oracle.lcs_pairs(c1.codes, c1.seq_off, i1, j1)
+    st_c1 = c1.cells() / (time.perf_counter() - t0) / 1e9
     return {"value": cells / wall / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
             "sample": f"{cores * npw} random pairs of the workload (seed {seed}), {cells:.3e} cells, "
-                      f"{cores} single-threaded processes, {wall:.1f} s wall"}
+                      f"{cores} single-threaded processes, {wall:.1f} s wall",
+            "single_thread_gcups": {"workload_10k_pairs": round(st_sample, 3), "c1_all_pairs": round(st_c1, 3)}}
 
 
 def run_main(b, steps, warmup, flags, tile_rows=1024, tune=True):
