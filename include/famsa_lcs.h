@@ -247,9 +247,11 @@ typedef struct famsa_mst_s famsa_mst_t;
 /* lengths: the k sequence lengths of the family (copied to `device`). */
 int famsa_mst_create(const uint32_t* lengths, uint32_t k, int device, famsa_mst_t** out);
 /* A famsa_lcs_tile_fn for device tiles: pass the famsa_mst_t* as `user`.
- * Orders its GPU work on tile->stream and returns once that work has
- * finished reading the tile (nonzero on a bad tile or a HIP error); calls on
- * one famsa_mst_t must not overlap. */
+ * Orders its GPU work on tile->stream, after the previous tile's merge
+ * whatever stream that one came on, and returns once that work has finished
+ * reading the tile (nonzero on a bad tile or a HIP error); calls on one
+ * famsa_mst_t must not overlap.  famsa_mst_result, _guide_tree and
+ * _get_stats wait for the last merge, not for the whole device. */
 int famsa_mst_consume(void* mst, const famsa_lcs_tile* tile);
 /* The forest's edges (k-1 of them once every pair has been seen): endpoints
  * u < v (family-local), their LCS and indel^2 (similarity LCS / indel^2).

@@ -387,6 +387,21 @@ struct famsa_mst_s {
   uint32_t slice_cap = 0;  // row slices the q* arrays hold
   PinMem hctl;
   uint64_t tiles = 0;
+  // Tiles arrive on whatever stream their producer used (a plan alternates
+  // two); this event marks the end of the last tile's work, and the next
+  // tile's work waits for it, so merges never overlap whatever the streams.
+  hipEvent_t last = nullptr;
+  bool has_last = false;
+  ~famsa_mst_s() {
+    if (last) {
+      if (has_last) (void)hipEventSynchronize(last);
+      (void)hipEventDestroy(last);
+    }
+  }
+  int wait_last() const {
+    if (has_last) FAMSA_HIP(hipEventSynchronize(last));
+    return 0;
+  }
   MstDev view() {
     MstDev m;
     m.len = len.as<uint32_t>();
@@ -438,6 +453,7 @@ int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
   const uint32_t r0 = t->row_begin, r1 = t->row_end;
   const bool has_tile = t->count && r1 > r0;
   if (r1 - r0 > 65535u) return set_error(FAMSA_LCS_EINVAL, "tiles of more than 65535 rows are not supported");
+  if (has_last) FAMSA_HIP(hipStreamWaitEvent(s, last, 0));  // the previous tile's merge, on any stream
   const uint32_t nblk = (uint32_t)((k + kScanCols - 1) / kScanCols);
   const uint32_t nslice = has_tile ? (r1 - r0 + kScanSlice - 1) / kScanSlice : 0;
   if (has_tile && ((uint64_t)nblk * (r1 - r0) > part_cap || nslice > slice_cap)) {
@@ -483,6 +499,8 @@ int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
   }
   hipLaunchKernelGGL(mst_tile_end, dim3(1), dim3(64), 0, s, m);
   FAMSA_HIP(hipGetLastError());
+  FAMSA_HIP(hipEventRecord(last, s));
+  has_last = true;
   std::swap(fu.p, nu.p);
   std::swap(fv.p, nv.p);
   std::swap(fL.p, nL.p);
@@ -525,6 +543,11 @@ int famsa_mst_create(const uint32_t* lengths, uint32_t k, int device, famsa_mst_
     delete m;
     return rc;
   }
+  if (hipEventCreateWithFlags(&m->last, hipEventDisableTiming) != hipSuccess) {
+    m->last = nullptr;
+    delete m;
+    return set_error(FAMSA_LCS_EDEVICE, "hipEventCreate failed");
+  }
   if ((k && hipMemcpy(m->len.p, lengths, (size_t)k * 4, hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemset(m->ctl.p, 0, sizeof(MstDev::Ctl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     delete m;
@@ -549,7 +572,8 @@ int famsa_mst_result(const famsa_mst_t* m, uint32_t* u, uint32_t* v, int64_t* lc
   clear_error();
   if (!m || !nedges) return set_error(FAMSA_LCS_EINVAL, "NULL argument");
   FAMSA_HIP(hipSetDevice(m->device));
-  FAMSA_HIP(hipDeviceSynchronize());
+  int rc = m->wait_last();
+  if (rc) return rc;
   MstDev::Ctl c;
   FAMSA_HIP(hipMemcpy(&c, m->ctl.p, sizeof c, hipMemcpyDeviceToHost));
   const uint32_t n = c.nf;
@@ -589,7 +613,8 @@ int famsa_mst_get_stats(const famsa_mst_t* m, uint64_t* tiles, uint64_t* rounds)
   clear_error();
   if (!m) return set_error(FAMSA_LCS_EINVAL, "mst is NULL");
   FAMSA_HIP(hipSetDevice(m->device));
-  FAMSA_HIP(hipDeviceSynchronize());
+  int rc = m->wait_last();
+  if (rc) return rc;
   MstDev::Ctl c;
   FAMSA_HIP(hipMemcpy(&c, m->ctl.p, sizeof c, hipMemcpyDeviceToHost));
   if (tiles) *tiles = m->tiles;
@@ -600,8 +625,7 @@ int famsa_mst_get_stats(const famsa_mst_t* m, uint64_t* tiles, uint64_t* rounds)
 void famsa_mst_destroy(famsa_mst_t* m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
-  (void)hipDeviceSynchronize();
-  delete m;
+  delete m;  // waits for the last tile's work
 }
 
 }  // extern "C"
