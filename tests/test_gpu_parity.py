@@ -72,6 +72,17 @@ def test_random_tile_mode_several_steps():
     check_all_tiles(b, tiles, 70)
 
 
+@pytest.mark.parametrize("flags", [B.DESCENDING, B.DESCENDING | B.NO_GRAPH, B.ONE_STREAM])
+def test_tile_mode_several_tiles_per_step(flags):
+    # steps of several tiles: the step's rows come first among the column
+    # positions, in length order, so pairs of two step rows land in the
+    # lower-indexed row's tile
+    b = inputs.random_family(300, 0, 700, 14)
+    tiles, info, _ = run(b, tile_rows=30, step_values=9000, flags=flags)
+    assert info.nsteps >= 3 and info.nsteps < info.ntiles
+    check_all_tiles(b, tiles, 30)
+
+
 def test_multi_family_uneven():
     fams, sizes = [], []
     rng = np.random.default_rng(4)
