@@ -19,6 +19,8 @@ the kernel's own.  Also reported, in the same JSON line:
   from the current kernel source and this configuration, else null;
 * two_streams: the same pass with consecutive steps on two compute streams
   (the library default), where one step's tail overlaps the next step;
+* plain: one pass of the plain baseline kernel over the same workload (one
+  pair per lane, one launch per tile), and the batched form's speed-up;
 * similarity_tiles: the same pass delivering float32 similarities instead of
   LCS values (the kernels' epilogue computes them);
 * gpu_single_linkage: the pass with device tiles feeding the GPU exact
@@ -364,6 +366,12 @@ def main():
                               "ms_per_step": round(1e3 * min(t2), 2),
                               "note": "same pass, consecutive steps on two compute streams (library default)"}
         print(f"[bench] two_streams {res['two_streams']}", file=sys.stderr, flush=True)
+        _, tp, _, _ = run_main(b, 1, 0, flags=B.PLAIN, tune=False)
+        res["plain"] = {"value": round(cells / tp[0] / 1e9, 1), "unit": "GCUPS", "ms_per_step": round(1e3 * tp[0], 2),
+                        "batched_over_plain": round(tp[0] / (ms / 1e3), 2),
+                        "note": "one pass of the plain baseline: one pair per lane, one launch per tile, each "
+                                "waiting for the previous tile's delivery"}
+        print(f"[bench] plain {res['plain']}", file=sys.stderr, flush=True)
         _, t3, _, _ = run_main(b, 2, 1, flags=B.OUT_SIM, tune=True)
         res["similarity_tiles"] = {"value": round(cells / min(t3) / 1e9, 1), "unit": "GCUPS",
                                    "ms_per_step": round(1e3 * min(t3), 2),
