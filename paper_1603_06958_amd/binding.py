@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5
 PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE, ONE_STREAM = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 OUT_INDEL, OUT_SIM = 0x40, 0x80
 PLAIN_ASYNC = 0x100
+TWO_STREAMS = 0x200
 VALUES_LCS, VALUES_INDEL, VALUES_SIM = 0, 1, 2
 MAX_LEN = 65535
 

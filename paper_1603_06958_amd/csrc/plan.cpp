@@ -1,11 +1,11 @@
 // famsa_lcs_plan / famsa_lcs_tiles / famsa_lcs_release: the C-ABI over the
 // runtime.  A plan owns the resident batch, the descriptor arrays of every
 // launch step, two device step buffers, two pinned host buffers, and (unless
-// disabled) instantiated hipGraphs -- one per compute stream and launch
-// signature -- that replay a step's launches.  Steps alternate between the
-// device's two shared compute streams so one step's tail overlaps the next
-// step's head, while the shared copy stream moves finished steps to pinned
-// memory and the caller's thread runs the tile callbacks.
+// disabled) instantiated hipGraphs -- one per buffer slot and launch
+// signature -- that replay a step's launches.  Steps run on the device's
+// shared compute stream (or alternate between two with
+// FAMSA_LCS_TWO_STREAMS), while the shared copy stream moves finished steps
+// to pinned memory and the caller's thread runs the tile callbacks.
 #include <stdio.h>
 #include <string.h>
 
@@ -42,7 +42,7 @@ struct famsa_lcs_plan_s {
   LaunchParams lp;
   StepExec exec;
   DevMem d_groups, d_lanes, d_items, d_prows, d_colmap, d_rowbase, d_ranges, d_ctl;
-  DevMem d_plainwork[2];  // per compute stream: steps on the two streams run concurrently
+  DevMem d_plainwork[2];  // per buffer slot: with two compute streams the slots' steps run concurrently
   DevMem d_carry[2];      // long-row carry scratch, per compute stream
   DevMem d_out[2];
   PinMem h_out[2];
@@ -66,10 +66,11 @@ struct famsa_lcs_plan_s {
   // output buffer slots: the plain baseline has one (each launch waits for
   // the previous tile's delivery) unless FAMSA_LCS_PLAIN_ASYNC asks for two
   int slots() const { return plain() && !(opt.flags & FAMSA_LCS_PLAIN_ASYNC) ? 1 : 2; }
-  // compute stream of a buffer slot: both slots share stream 0 under
-  // ONE_STREAM and in the plain baseline
+  // compute stream of a buffer slot: both slots share stream 0 unless
+  // FAMSA_LCS_TWO_STREAMS asks for one stream per slot (never in the plain
+  // baseline)
   hipStream_t cstream(int slot) const {
-    return (opt.flags & (FAMSA_LCS_ONE_STREAM | FAMSA_LCS_PLAIN)) ? cs[0] : cs[slot];
+    return (opt.flags & FAMSA_LCS_TWO_STREAMS) && !plain() ? cs[slot] : cs[0];
   }
   // Steps replay captured graphs unless FAMSA_LCS_NO_GRAPH asks for direct
   // launches (which are timed per kernel class with events).

@@ -85,10 +85,12 @@ int normalize_options(const famsa_lcs_options* in, Opts* o) {
   if (d.device < 0) return set_error(FAMSA_LCS_EINVAL, "device %d < 0", d.device);
   const uint32_t known = FAMSA_LCS_PLAIN | FAMSA_LCS_DESCENDING | FAMSA_LCS_DEVICE_TILES | FAMSA_LCS_NO_GRAPH |
                          FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM | FAMSA_LCS_OUT_INDEL | FAMSA_LCS_OUT_SIM |
-                         FAMSA_LCS_PLAIN_ASYNC;
+                         FAMSA_LCS_PLAIN_ASYNC | FAMSA_LCS_TWO_STREAMS;
   if (d.flags & ~known) return set_error(FAMSA_LCS_EINVAL, "unknown flag bits 0x%x", d.flags & ~known);
   if ((d.flags & FAMSA_LCS_OUT_INDEL) && (d.flags & FAMSA_LCS_OUT_SIM))
     return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_OUT_INDEL and FAMSA_LCS_OUT_SIM exclude each other");
+  if ((d.flags & FAMSA_LCS_ONE_STREAM) && (d.flags & FAMSA_LCS_TWO_STREAMS))
+    return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_ONE_STREAM and FAMSA_LCS_TWO_STREAMS exclude each other");
   if ((d.flags & FAMSA_LCS_PLAIN_ASYNC) && !(d.flags & FAMSA_LCS_PLAIN))
     return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_PLAIN_ASYNC needs FAMSA_LCS_PLAIN");
   if (d.cols_per_item > (1u << 20)) return set_error(FAMSA_LCS_EINVAL, "cols_per_item %u too large", d.cols_per_item);

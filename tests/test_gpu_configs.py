@@ -46,10 +46,10 @@ def test_c4_sampled_bench_configuration():
 
 @pytest.mark.timeout(600)
 def test_c4_sampled_two_streams_with_graphs():
-    # the library default (graph replays on two compute streams)
+    # graph replays alternating between two compute streams
     b = inputs.c4()
     s = Sampler(b, per_tile=20, seed=4, bound_check_every=49)
-    with B.Plan.from_batch(b) as p:
+    with B.Plan.from_batch(b, flags=B.TWO_STREAMS) as p:
         p.run(s)
     assert s.ntiles == 98 and s.count == b.pairs()
     s.check()

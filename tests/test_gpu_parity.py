@@ -72,7 +72,8 @@ def test_random_tile_mode_several_steps():
     check_all_tiles(b, tiles, 70)
 
 
-@pytest.mark.parametrize("flags", [B.DESCENDING, B.DESCENDING | B.NO_GRAPH, B.ONE_STREAM])
+@pytest.mark.parametrize("flags", [B.DESCENDING, B.DESCENDING | B.NO_GRAPH, B.TWO_STREAMS,
+                                   B.TWO_STREAMS | B.NO_GRAPH | B.DESCENDING])
 def test_tile_mode_several_tiles_per_step(flags):
     # steps of several tiles: the step's rows come first among the column
     # positions, in length order, so pairs of two step rows land in the
