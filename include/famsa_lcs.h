@@ -68,12 +68,12 @@ typedef enum famsa_lcs_status {
 #define FAMSA_LCS_OUT_SIM      0x80u /* tiles hold the similarity LCS / indel^2 as float32 (the float rounding
                                         of the correctly rounded double; +infinity when indel = 0) instead of
                                         LCS (Methods, "Pairwise similarities calculation"); excludes OUT_INDEL */
-#define FAMSA_LCS_TWO_STREAMS  0x200u /* alternate consecutive launch steps between two compute streams, so a
-                                         step's tail overlaps the next step's head (on a single family of
-                                         k = 100,000 this is 3% slower with graphs and equal without) */
 #define FAMSA_LCS_PLAIN_ASYNC  0x100u /* with FAMSA_LCS_PLAIN only: two output buffers on one compute stream, and
                                          each tile's launch is issued without waiting for the previous tile's
                                          delivery (the plain kernels with no host synchronisation between them) */
+#define FAMSA_LCS_TWO_STREAMS  0x200u /* alternate consecutive launch steps between two compute streams, so a
+                                         step's tail overlaps the next step's head (on a single family of
+                                         k = 100,000 this is 3% slower with graphs and equal without) */
 
 /* What a tile's values are (famsa_lcs_tile.values). */
 #define FAMSA_LCS_VALUES_LCS   0u
