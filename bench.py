@@ -182,6 +182,52 @@ def run_gpu_single_linkage(b, passes=2):
             "delivery": "device tiles, graph replays on one compute stream"}
 
 
+def run_consumer_alone(b, reps=2):
+    """The GPU single-linkage consumer alone: every tile of the workload is
+    first computed into one device buffer (the whole matrix, 20 GB for c4),
+    then the consumer is timed over the stored tiles; best of `reps`."""
+    import ctypes
+    import torch
+    from paper_1603_06958_amd import binding as B
+    k = b.nseq
+    buf = torch.empty(k * (k - 1) // 2, dtype=torch.int32, device="cuda")
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    tiles, off = [], [0]
+
+    def keep(t):
+        n = int(t.count)
+        if n and hip.hipMemcpyAsync(buf.data_ptr() + 4 * off[0], ctypes.cast(t.lcs, ctypes.c_void_p), 4 * n, 3,
+                                    t.stream) != 0:
+            return 1
+        tiles.append((int(t.row_begin), int(t.row_end), off[0], n))
+        off[0] += n
+        return 0
+
+    with B.Plan.from_batch(b, flags=B.DEVICE_TILES, step_values=STEP_VALUES) as p:
+        p.run(keep)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream().cuda_stream
+    best, rounds = None, 0
+    for _ in range(reps):
+        m = B.Mst(b.lengths())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r0, r1, o, n in tiles:
+            t = B.Tile(tile_index=0, family=0, k=k, row_begin=r0, row_end=r1,
+                       lcs=ctypes.cast(ctypes.c_void_p(buf.data_ptr() + 4 * o), ctypes.POINTER(ctypes.c_int32)),
+                       count=n, stream=stream, values=B.VALUES_LCS)
+            B.check(0 if B.lib().famsa_mst_consume(m.handle, ctypes.byref(t)) == 0 else B.EDEVICE)
+        edges = len(m.result()[0])
+        dt = time.perf_counter() - t0
+        rounds = m.stats()[1]
+        m.close()
+        best = dt if best is None else min(best, dt)
+    del buf
+    return {"s": round(best, 4), "tiles": len(tiles), "tree_edges": edges, "boruvka_rounds": rounds,
+            "ms_per_tile": round(1e3 * best / max(1, len(tiles)), 3)}
+
+
 def run_host_slink():
     """Host SLINK (exact similarities) over all of c2's tiles: the consumer
     alone (tiles already in host memory, fed last row first), and the whole
@@ -302,6 +348,8 @@ def main():
                     help="skip the two-stream, GPU single-linkage and host SLINK measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for scaling HBM byte counters)")
+    ap.add_argument("--consumer-alone", action="store_true",
+                    help="only time the GPU single-linkage consumer over the workload's tiles kept in HBM")
     a = ap.parse_args()
     if a.copy_calibration:
         import torch
@@ -311,6 +359,11 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return
+    if a.consumer_alone:
+        from paper_1603_06958_amd import inputs
+        print(json.dumps({"consumer_alone": run_consumer_alone(getattr(inputs, a.workload)()),
+                          "workload": a.workload}), flush=True)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the stage runs on a single MI355X here "
