@@ -132,8 +132,14 @@ __global__ void mst_tile_begin(MstDev m) {
 // a candidate for both ends.  A row's best over the block's columns is a wave
 // reduction, stored as partial (row, bx); a column's best over the slice's
 // rows is reduced over the four waves in LDS and stored as partial (sy, j).
+//
+// Components only grow during a tile's rounds, so the candidates of a row or
+// a column only shrink: a partial whose edge still joins two components is
+// still the best of its set.  After the tile's first round a block therefore
+// recomputes only the partials whose edge has since fallen inside one
+// component, and reads only the elements those partials need.
 __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restrict__ tile, uint32_t r0, uint32_t r1,
-                                                uint32_t nblk) {
+                                                uint32_t nblk, uint32_t first) {
   if (m.ctl->done) return;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t jb = blockIdx.x * kScanCols;
@@ -141,6 +147,8 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
   uint64_t ck[4], cid[4];
   int32_t cL[4];
   uint32_t cc[4], cl[4];
+  bool cnew[4];  // column partial (sy, j) to recompute
+  bool anycol = false;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     ck[c] = 0;
@@ -149,36 +157,82 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
     const uint32_t j = jb + 64u * c + lane;
     cc[c] = j < m.k ? m.comp[j] : 0u;
     cl[c] = j < m.k ? m.len[j] : 0u;
+    cnew[c] = j < m.k;
+    if (!first && j < m.k) {
+      const uint64_t q = (uint64_t)blockIdx.y * k + j;
+      // no candidate then means none now; else recompute once its row end joined j's component
+      cnew[c] = m.qkey[q] != 0 && m.comp[(uint32_t)(m.qid[q] / k)] == cc[c];
+    }
+    anycol |= cnew[c];
   }
+  anycol = __any(anycol);
   const uint32_t i0 = r0 + blockIdx.y * kScanSlice;
   const uint32_t iend = min(min(r1, i0 + kScanSlice), jb + kScanCols - 1u);  // rows with a column of the block after them
-  for (uint32_t i = i0 + wave; i < iend; i += kScanWaves) {
-    const uint32_t ci = m.comp[i], li = m.len[i];
-    const uint64_t off = row_off(k, r0, i);  // LCS(i, j) at off + j - i - 1
-    int32_t L[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {  // only pairs across components are read: later rounds read little
-      const uint32_t j = jb + 64u * c + lane;
-      L[c] = (j > i && j < m.k && cc[c] != ci) ? tile[off + (j - i - 1u)] : 0;
+  // The wave's rows are i0 + wave + kScanWaves t.  Lane t reads row t's
+  // component, length and partial up front, all rows at once; rows are then
+  // taken kChunk at a time, each group's tile loads issued together.
+  constexpr uint32_t kRows = kScanSlice / kScanWaves;
+  constexpr uint32_t kChunk = 4;  // rows whose tile loads are in flight together (8: slower)
+  const uint32_t myrow = i0 + wave + kScanWaves * lane;
+  const bool myok = lane < kRows && myrow < iend;
+  uint32_t mci = 0, mli = 0;
+  bool mnew = false;
+  if (myok) {
+    mci = m.comp[myrow];
+    mli = m.len[myrow];
+    mnew = true;
+    if (!first) {
+      const uint64_t p = (uint64_t)(myrow - r0) * nblk + blockIdx.x;
+      mnew = m.pkey[p] != 0 && m.comp[(uint32_t)(m.pid[p] % k)] == mci;
     }
-    uint64_t rk = 0, ri = ~0ull;
-    int32_t rL = 0;
+  }
+  const uint32_t nrows = (uint32_t)__popcll(__ballot(myok));  // rows 0..nrows-1 of the wave exist
+  const uint64_t newmask = __ballot(mnew);
+  for (uint32_t t0 = 0; t0 < nrows && (anycol || (newmask >> t0) != 0); t0 += kChunk) {
+    int32_t L[kChunk][4];
+    uint32_t ci[kChunk], li[kChunk];
+    bool rnew[kChunk];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint32_t j = jb + 64u * c + lane;
-      if (j > i && j < m.k && cc[c] != ci) {
-        const uint64_t key = sim_key(L[c], li, cl[c]);
-        const uint64_t id = (uint64_t)i * k + j;
-        take(ck[c], cid[c], cL[c], key, id, L[c]);
-        take(rk, ri, rL, key, id, L[c]);
+    for (int u = 0; u < (int)kChunk; ++u) {
+      const uint32_t t = t0 + (uint32_t)u;
+      const bool live = t < nrows;
+      const uint32_t i = i0 + wave + kScanWaves * t;
+      ci[u] = (uint32_t)__shfl((int)mci, (int)(t & 63u), 64);
+      li[u] = (uint32_t)__shfl((int)mli, (int)(t & 63u), 64);
+      rnew[u] = live && ((newmask >> t) & 1ull);
+      const uint64_t off = row_off(k, r0, i);  // LCS(i, j) at off + j - i - 1
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {  // only pairs across components, and only those a partial needs
+        const uint32_t j = jb + 64u * c + lane;
+        L[u][c] = (live && j > i && j < m.k && cc[c] != ci[u] && (rnew[u] || cnew[c])) ? tile[off + (j - i - 1u)] : 0;
       }
     }
-    wave_best(rk, ri, rL);
-    if (lane == 0) {
-      const uint64_t p = (uint64_t)(i - r0) * nblk + blockIdx.x;
-      m.pkey[p] = rk;
-      m.pid[p] = ri;
-      m.pL[p] = rL;
+#pragma unroll
+    for (int u = 0; u < (int)kChunk; ++u) {
+      const uint32_t t = t0 + (uint32_t)u;
+      if (t >= nrows) break;
+      const uint32_t i = i0 + wave + kScanWaves * t;
+      uint64_t rk = 0, ri = ~0ull;
+      int32_t rL = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint32_t j = jb + 64u * c + lane;
+        if (j > i && j < m.k && cc[c] != ci[u] && (rnew[u] || cnew[c])) {
+          const uint64_t key = sim_key(L[u][c], li[u], cl[c]);
+          const uint64_t id = (uint64_t)i * k + j;
+          if (cnew[c]) take(ck[c], cid[c], cL[c], key, id, L[u][c]);
+          take(rk, ri, rL, key, id, L[u][c]);
+        }
+      }
+      if (rnew[u]) {
+        if (__any(rk != 0)) wave_best(rk, ri, rL);  // else no lane has a candidate: (0, ~0, 0) as it is
+        if (lane == 0) {
+          const uint64_t p = (uint64_t)(i - r0) * nblk + blockIdx.x;
+          m.pkey[p] = rk;
+          m.pid[p] = ri;
+          m.pL[p] = rL;
+        }
+      }
     }
   }
   __shared__ uint64_t sk[kScanWaves / 2][kScanCols], si[kScanWaves / 2][kScanCols];
@@ -204,7 +258,7 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const uint32_t j = jb + 64u * c + lane;
-      if (j >= m.k) continue;
+      if (!cnew[c]) continue;
       const uint64_t q = (uint64_t)blockIdx.y * k + j;
       m.qkey[q] = ck[c];
       m.qid[q] = cid[c];
@@ -292,18 +346,45 @@ __global__ void mst_forest_L(MstDev m) {
 // skips most atomics: once a component holds a large key few vertices beat it.
 __global__ void mst_vertex_merge(MstDev m) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m.ctl->done || v >= m.k) return;
-  uint64_t bk = m.vkey[v], bi = m.vid[v];
-  int32_t bL = m.vL[v];
-  if (m.wkey[v]) {
-    take(bk, bi, bL, m.wkey[v], m.wid[v], m.wL[v]);
-    m.vkey[v] = bk;
-    m.vid[v] = bi;
-    m.vL[v] = bL;
+  if (m.ctl->done) return;
+  const bool ok = v < m.k;
+  uint64_t bk = 0;
+  uint32_t c = 0;
+  if (ok) {
+    uint64_t bi = m.vid[v];
+    int32_t bL = m.vL[v];
+    bk = m.vkey[v];
+    if (m.wkey[v]) {
+      take(bk, bi, bL, m.wkey[v], m.wid[v], m.wL[v]);
+      m.vkey[v] = bk;
+      m.vid[v] = bi;
+      m.vL[v] = bL;
+    }
+    c = m.comp[v];
   }
-  if (bk == 0) return;
-  uint64_t* slot = &m.ckey[m.comp[v]];
-  if (bk > *slot) atomicMax((unsigned long long*)slot, (unsigned long long)bk);
+  // Late in a tile most vertices share one large component, and their
+  // atomics on its slot would queue up: the lanes of a wave in the
+  // component of its first candidate take their maximum first, and one lane
+  // offers it.  Every lane stays in the wave for the shuffles.
+  const bool cand = ok && bk != 0;
+  const uint64_t candmask = __ballot(cand);
+  if (candmask == 0) return;
+  const int first = __ffsll((unsigned long long)candmask) - 1;
+  const uint32_t lead = (uint32_t)__shfl((int)c, first, 64);
+  uint64_t x = cand && c == lead ? bk : 0;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t y = __shfl_xor(x, d, 64);
+    x = y > x ? y : x;
+  }
+  if ((int)__lane_id() == first) {
+    uint64_t* slot = &m.ckey[lead];
+    if (x > *slot) atomicMax((unsigned long long*)slot, (unsigned long long)x);
+  }
+  if (cand && c != lead) {
+    uint64_t* slot = &m.ckey[c];
+    if (bk > *slot) atomicMax((unsigned long long*)slot, (unsigned long long)bk);
+  }
 }
 
 __global__ void mst_comp_id(MstDev m) {
@@ -476,7 +557,9 @@ int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
   uint32_t queued = 0;
   for (uint32_t batch = 6;; batch = 2) {
     for (uint32_t r = 0; r < batch; ++r) {
-      if (has_tile) hipLaunchKernelGGL(mst_scan, dim3(nblk, nslice), dim3(64 * kScanWaves), 0, s, m, t->lcs, r0, r1, nblk);
+      const uint32_t first = queued == 0 && r == 0;  // the tile's first round computes every partial
+      if (has_tile)
+        hipLaunchKernelGGL(mst_scan, dim3(nblk, nslice), dim3(64 * kScanWaves), 0, s, m, t->lcs, r0, r1, nblk, first);
       hipLaunchKernelGGL(mst_col_reduce, gk, dim3(256), 0, s, m, nslice);
       if (has_tile) hipLaunchKernelGGL(mst_row_reduce, dim3(r1 - r0), dim3(64), 0, s, m, r0, nblk);
       hipLaunchKernelGGL(mst_forest_key, gk, dim3(256), 0, s, m);
