@@ -139,10 +139,11 @@ __global__ void mst_tile_begin(MstDev m) {
 // recomputes only the partials whose edge has since fallen inside one
 // component, and reads only the elements those partials need.
 __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restrict__ tile, uint32_t r0, uint32_t r1,
-                                                uint32_t nblk, uint32_t first) {
+                                                uint32_t nblk, uint32_t bx0, uint32_t first) {
   if (m.ctl->done) return;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t jb = blockIdx.x * kScanCols;
+  const uint32_t bx = bx0 + blockIdx.x;  // blocks left of column r0 + 1 hold no pair and are not launched
+  const uint32_t jb = bx * kScanCols;
   const uint64_t k = m.k;
   uint64_t ck[4], cid[4];
   int32_t cL[4];
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
     mli = m.len[myrow];
     mnew = true;
     if (!first) {
-      const uint64_t p = (uint64_t)(myrow - r0) * nblk + blockIdx.x;
+      const uint64_t p = (uint64_t)(myrow - r0) * nblk + bx;
       mnew = m.pkey[p] != 0 && m.comp[(uint32_t)(m.pid[p] % k)] == mci;
     }
   }
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
       if (rnew[u]) {
         if (__any(rk != 0)) wave_best(rk, ri, rL);  // else no lane has a candidate: (0, ~0, 0) as it is
         if (lane == 0) {
-          const uint64_t p = (uint64_t)(i - r0) * nblk + blockIdx.x;
+          const uint64_t p = (uint64_t)(i - r0) * nblk + bx;
           m.pkey[p] = rk;
           m.pid[p] = ri;
           m.pL[p] = rL;
@@ -269,16 +270,17 @@ __global__ __launch_bounds__(256) void mst_scan(MstDev m, const int32_t* __restr
 
 // Column results and per-round reset: vertex j takes the best of its column
 // partials over the row slices; its forest and component slots are cleared.
-__global__ void mst_col_reduce(MstDev m, uint32_t nslice) {
+__global__ void mst_col_reduce(MstDev m, uint32_t r0, uint32_t nslice) {
   if (m.ctl->done) return;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.k) return;
   uint64_t bk = 0, bi = ~0ull;
   int32_t bL = 0;
-  for (uint32_t y = 0; y < nslice; ++y) {
-    const uint64_t q = (uint64_t)y * m.k + j;
-    take(bk, bi, bL, m.qkey[q], m.qid[q], m.qL[q]);
-  }
+  if (j > r0)  // a column at or before the tile's first row has no pair in it (and no partials)
+    for (uint32_t y = 0; y < nslice; ++y) {
+      const uint64_t q = (uint64_t)y * m.k + j;
+      take(bk, bi, bL, m.qkey[q], m.qid[q], m.qL[q]);
+    }
   m.vkey[j] = bk;
   m.vid[j] = bi;
   m.vL[j] = bL;
@@ -552,6 +554,8 @@ int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
   }
   const MstDev m = view();
   const dim3 gk = grid_for(k);
+  // first column block holding a column after row r0 (has_tile: r0 + 1 < k, so bx0 < nblk)
+  const uint32_t bx0 = (uint32_t)((r0 + 1ull) / kScanCols);
   hipLaunchKernelGGL(mst_tile_begin, gk, dim3(256), 0, s, m);
   const uint32_t kmax_rounds = 2 + (uint32_t)ceil(log2((double)std::max<uint32_t>(k, 2)));
   uint32_t queued = 0;
@@ -559,8 +563,9 @@ int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
     for (uint32_t r = 0; r < batch; ++r) {
       const uint32_t first = queued == 0 && r == 0;  // the tile's first round computes every partial
       if (has_tile)
-        hipLaunchKernelGGL(mst_scan, dim3(nblk, nslice), dim3(64 * kScanWaves), 0, s, m, t->lcs, r0, r1, nblk, first);
-      hipLaunchKernelGGL(mst_col_reduce, gk, dim3(256), 0, s, m, nslice);
+        hipLaunchKernelGGL(mst_scan, dim3(nblk - bx0, nslice), dim3(64 * kScanWaves), 0, s, m, t->lcs, r0, r1, nblk,
+                           bx0, first);
+      hipLaunchKernelGGL(mst_col_reduce, gk, dim3(256), 0, s, m, r0, nslice);
       if (has_tile) hipLaunchKernelGGL(mst_row_reduce, dim3(r1 - r0), dim3(64), 0, s, m, r0, nblk);
       hipLaunchKernelGGL(mst_forest_key, gk, dim3(256), 0, s, m);
       hipLaunchKernelGGL(mst_forest_id, gk, dim3(256), 0, s, m);
