@@ -60,7 +60,6 @@ struct MstDev {
   int32_t* wL;
   uint64_t* ckey;     // best outgoing edge per component
   uint64_t* cid;
-  int32_t* cL;
   uint64_t* pkey;     // row partials: best edge of each (tile row, column block)
   uint64_t* pid;
   int32_t* pL;
@@ -396,28 +395,27 @@ __global__ void mst_comp_id(MstDev m) {
   if (m.vkey[v] == m.ckey[c]) atomicMin((unsigned long long*)&m.cid[c], (unsigned long long)m.vid[v]);
 }
 
-__global__ void mst_comp_L(MstDev m) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m.ctl->done || v >= m.k || m.vkey[v] == 0) return;
-  const uint32_t c = m.comp[v];
-  if (m.vkey[v] == m.ckey[c] && m.vid[v] == m.cid[c]) m.cL[c] = m.vL[v];  // one vertex per component matches
-}
-
 // Hook every component with an outgoing edge onto the component at its other
-// end.  Two components that chose the same edge hook once: the larger onto
-// the smaller.  Each hook adds its edge to the new forest.
+// end.  The one vertex of the component that holds its chosen edge (the
+// candidate key and id equal the component's) does it, so the edge's LCS is
+// at hand.  Two components that chose the same edge hook once: the larger
+// onto the smaller.  Each hook adds its edge to the new forest.
 __global__ void mst_hook(MstDev m) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m.ctl->done || c >= m.k || m.comp[c] != c || m.ckey[c] == 0) return;
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m.ctl->done || v >= m.k) return;
+  const uint64_t key = m.vkey[v];
+  if (key == 0) return;
+  const uint32_t c = m.comp[v];
+  if (key != m.ckey[c] || m.vid[v] != m.cid[c]) return;
   const uint64_t id = m.cid[c];
-  const uint32_t u = (uint32_t)(id / m.k), v = (uint32_t)(id % m.k);
-  const uint32_t d = m.comp[u] == c ? m.comp[v] : m.comp[u];
+  const uint32_t u = (uint32_t)(id / m.k), w = (uint32_t)(id % m.k);
+  const uint32_t d = m.comp[u] == c ? m.comp[w] : m.comp[u];
   if (m.cid[d] == id && c < d) return;  // mutual choice: d hooks onto c
   m.parent[c] = d;
   const uint32_t slot = atomicAdd(&m.ctl->nnew, 1u);
   m.nu[slot] = u;
-  m.nv[slot] = v;
-  m.nL[slot] = m.cL[c];
+  m.nv[slot] = w;
+  m.nL[slot] = m.vL[v];
   atomicAdd(&m.ctl->hooks, 1u);
 }
 
@@ -464,7 +462,7 @@ using namespace famsa;
 struct famsa_mst_s {
   uint32_t k = 0;
   int device = 0;
-  DevMem len, comp, parent, vkey, vid, vL, wkey, wid, wL, ckey, cid, cL, pkey, pid, pL, qkey, qid, qL;
+  DevMem len, comp, parent, vkey, vid, vL, wkey, wid, wL, ckey, cid, pkey, pid, pL, qkey, qid, qL;
   DevMem fu, fv, fL, nu, nv, nL, ctl;
   uint64_t part_cap = 0;   // row partials the p* arrays hold
   uint32_t slice_cap = 0;  // row slices the q* arrays hold
@@ -499,7 +497,6 @@ struct famsa_mst_s {
     m.wL = wL.as<int32_t>();
     m.ckey = ckey.as<uint64_t>();
     m.cid = cid.as<uint64_t>();
-    m.cL = cL.as<int32_t>();
     m.pkey = pkey.as<uint64_t>();
     m.pid = pid.as<uint64_t>();
     m.pL = pL.as<int32_t>();
@@ -572,7 +569,6 @@ int famsa_mst_s::merge_tile(const famsa_lcs_tile* t, hipStream_t s) {
       hipLaunchKernelGGL(mst_forest_L, gk, dim3(256), 0, s, m);
       hipLaunchKernelGGL(mst_vertex_merge, gk, dim3(256), 0, s, m);
       hipLaunchKernelGGL(mst_comp_id, gk, dim3(256), 0, s, m);
-      hipLaunchKernelGGL(mst_comp_L, gk, dim3(256), 0, s, m);
       hipLaunchKernelGGL(mst_hook, gk, dim3(256), 0, s, m);
       hipLaunchKernelGGL(mst_jump, gk, dim3(256), 0, s, m);
       hipLaunchKernelGGL(mst_relabel, gk, dim3(256), 0, s, m);
@@ -624,7 +620,7 @@ int famsa_mst_create(const uint32_t* lengths, uint32_t k, int device, famsa_mst_
   if ((rc = m->len.alloc(n * 4)) || (rc = m->comp.alloc(n * 4)) || (rc = m->parent.alloc(n * 4)) ||
       (rc = m->vkey.alloc(n * 8)) || (rc = m->vid.alloc(n * 8)) || (rc = m->vL.alloc(n * 4)) ||
       (rc = m->wkey.alloc(n * 8)) || (rc = m->wid.alloc(n * 8)) || (rc = m->wL.alloc(n * 4)) ||
-      (rc = m->ckey.alloc(n * 8)) || (rc = m->cid.alloc(n * 8)) || (rc = m->cL.alloc(n * 4)) ||
+      (rc = m->ckey.alloc(n * 8)) || (rc = m->cid.alloc(n * 8)) ||
       (rc = m->fu.alloc(n * 4)) || (rc = m->fv.alloc(n * 4)) || (rc = m->fL.alloc(n * 4)) ||
       (rc = m->nu.alloc(n * 4)) || (rc = m->nv.alloc(n * 4)) || (rc = m->nL.alloc(n * 4)) ||
       (rc = m->ctl.alloc(sizeof(MstDev::Ctl))) || (rc = m->hctl.alloc(sizeof(MstDev::Ctl)))) {
