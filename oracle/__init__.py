@@ -18,6 +18,9 @@ Contents, each following the FAMSA paper (Methods):
   tree") by its plain definition: Kruskal's algorithm over all pairs, giving
   the merge heights and the cophenetic similarity of every pair.
 * ``guide_tree`` -- the same clustering as a merge list (the guide tree).
+* ``oracle.profile`` -- aligning one sequence to a profile ("Progressive
+  construction of the alignment", "Gap types and costs determination"):
+  column costs, gap-type rules and the affine-gap DP (``profile_dp.c``).
 * ``oracle.gapped`` -- the gapped sequence representation ("Progressive
   construction of the alignment", Fig. 1) computed from explicit gapped
   strings.
@@ -36,16 +39,16 @@ from typing import List, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "lcs_dp.c")
+_SRCS = [os.path.join(_HERE, "lcs_dp.c"), os.path.join(_HERE, "profile_dp.c")]
 _LIB = os.path.join(_HERE, "liboracle_lcs.so")
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile lcs_dp.c into liboracle_lcs.so with gcc (-O2, no vectorisation flags)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile lcs_dp.c and profile_dp.c into liboracle_lcs.so with gcc (-O2, no vectorisation flags)."""
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +68,11 @@ def _load():
         lib.oracle_lcs_rows.argtypes = [u8p, u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.c_uint64, i32p]
         lib.oracle_lcs_rows.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_profile_dp.argtypes = [ctypes.c_uint32, u8p, ctypes.c_uint32, ctypes.c_uint32, i64p, i64p, i64p,
+                                          i64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                          i64p, u8p, ctypes.POINTER(ctypes.c_uint32)]
+        lib.oracle_profile_dp.restype = ctypes.c_int
         _lib = lib
     return _lib
 

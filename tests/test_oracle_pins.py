@@ -148,3 +148,41 @@ def test_pairs_and_rows_layout():
     ia = np.array([0, 3, 12]); ib = np.array([5, 3, 1])
     got = oracle.lcs_pairs(b.codes, b.seq_off, ia, ib)
     assert got.tolist() == [oracle.lcs(b.seq(x), b.seq(y)) for x, y in zip(ia, ib)]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_full_matrix_pairwise(seed):
+    """full_matrix (the k x k matrix the linkage pins and GPU consumer tests
+    read) against one oracle.lcs call per pair: every (i, j) in both triangles,
+    the symmetry and the diagonal (LCS(a, a) = |a|), on families holding empty
+    and repeated sequences; on tiny families also against brute force."""
+    rng = np.random.default_rng(300 + seed)
+    k = [17, 23, 9][seed]
+    sigma = [20, 3, 2][seed]
+    hi = [40, 14, 8][seed]
+    seqs = [rng.integers(0, sigma, rng.integers(0, hi)).astype(np.uint8) for _ in range(k)]
+    seqs[2] = np.zeros(0, np.uint8)            # empty
+    seqs[5] = seqs[1].copy()                   # repeated
+    seqs[k - 1] = seqs[0][::-1].copy()         # reversal of another
+    seqs.insert(3, np.zeros(0, np.uint8))      # second empty
+    k += 1
+    codes = np.concatenate(seqs) if sum(s.size for s in seqs) else np.zeros(0, np.uint8)
+    off = np.zeros(k + 1, np.uint64)
+    off[1:] = np.cumsum([s.size for s in seqs])
+    # a family inside a larger batch: one leading sequence before it
+    lead = rng.integers(0, sigma, 7).astype(np.uint8)
+    codes2 = np.concatenate([lead, codes])
+    off2 = np.concatenate([[0], off + lead.size]).astype(np.uint64)
+    for cc, oo, base in ((codes, off, 0), (codes2, off2, 1)):
+        M = oracle.full_matrix(cc, oo, base, k)
+        assert M.shape == (k, k)
+        assert np.array_equal(M, M.T)
+        for i in range(k):
+            assert M[i, i] == seqs[i].size
+            for j in range(k):
+                if i != j:
+                    assert M[i, j] == oracle.lcs(seqs[i], seqs[j]), (i, j)
+        if seed == 2:
+            for i in range(k):
+                for j in range(i + 1, k):
+                    assert M[i, j] == brute_lcs(seqs[i].tolist(), seqs[j].tolist()), (i, j)
