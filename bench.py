@@ -62,6 +62,7 @@ METRIC = "GCUPS for all-pairs bit-parallel LCS (k=100k), batched vs plain; serve
 PEAK_INT_OPS = 256 * 128 * 2.4e9
 OPS_PER_CELL = 3.0 / 32.0             # AND + ADDC + BITOP3 per 32-cell dword-step
 STEP_VALUES = 1 << 28                 # int32 results per launch step (1 GiB per buffer)
+CPU_SHARE = 16                        # host cores a one-GPU machine grants a job
 TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "lcs_fast_c4_hbm_traffic.txt")
 # the kernels and the constants that shape them (class bounds, LDS layout)
 KERNEL_SOURCES = [os.path.join(HERE, "paper_1603_06958_amd", "csrc", f) for f in ("lcs_kernels.hip", "lcs_common.h")]
@@ -89,10 +90,12 @@ def cpu_baseline(b, seconds_target=12.0, seed=7):
     dt = time.perf_counter() - t0
     rate1 = float((L[ia] * L[ib]).sum()) / max(dt, 1e-9)
     try:
-        cores = len(os.sched_getaffinity(0))
+        visible = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        visible = os.cpu_count() or 1
+    # the GPU machine's CPU share is 16 cores, whatever the affinity mask shows:
+    # one single-threaded worker process per core of that share
+    cores = max(1, min(visible, CPU_SHARE))
     per_worker_cells = rate1 * seconds_target
     mean_cells = float((L.mean()) ** 2)
     npw = max(50, int(per_worker_cells / mean_cells))
@@ -120,6 +123,7 @@ def cpu_baseline(b, seconds_target=12.0, seed=7):
     oracle.lcs_pairs(c1.codes, c1.seq_off, i1, j1)
     st_c1 = c1.cells() / (time.perf_counter() - t0) / 1e9
     return {"value": cells / wall / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
+            "affinity_cpus": visible, "cpu_share": CPU_SHARE,
             "sample": f"{cores * npw} random pairs of the workload (seed {seed}), {cells:.3e} cells, "
                       f"{cores} single-threaded processes, {wall:.1f} s wall",
             "single_thread_gcups": {"workload_10k_pairs": round(st_sample, 3), "c1_all_pairs": round(st_c1, 3)}}
@@ -299,6 +303,24 @@ def traffic_per_launch(kernel):
     return None, "kernel not in the counter summary"
 
 
+def run_peak(variants=(0,), blocks_per_cu=8, iters=20000):
+    """The integer-VALU ceiling measured by the library's register-only chains
+    of the LCS step's instructions (famsa_valu_peak); best of three each."""
+    from paper_1603_06958_amd import binding as B
+    names = {0: "recurrence (and, addc chain, bitop3)", 1: "v_and_b32", 2: "v_addc_co_u32 chain", 3: "v_bitop3_b32"}
+    out = {}
+    for v in variants:
+        best = None
+        for _ in range(3):
+            r = B.valu_peak(v, blocks_per_cu, iters)
+            if best is None or r.ops_per_s > best.ops_per_s:
+                best = r
+        out[names[v]] = {"tops_per_s": round(best.ops_per_s / 1e12, 3), "clock_ghz": round(best.clock_ghz, 3),
+                         "lane_ops_per_clk_per_cu": round(best.lane_ops_per_clk_per_cu, 2),
+                         "ms": round(best.ms, 3), "cus": int(best.cus)}
+    return out
+
+
 def run_c3(passes=5):
     from paper_1603_06958_amd import binding as B, inputs
     b = inputs.c3()
@@ -348,6 +370,8 @@ def main():
                     help="skip the two-stream, GPU single-linkage and host SLINK measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for scaling HBM byte counters)")
+    ap.add_argument("--peak", action="store_true",
+                    help="only run the integer-VALU ceiling microbenchmark (all four instruction variants)")
     ap.add_argument("--consumer-alone", action="store_true",
                     help="only time the GPU single-linkage consumer over the workload's tiles kept in HBM")
     a = ap.parse_args()
@@ -359,6 +383,9 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return
+    if a.peak:
+        print(json.dumps({"valu_peak": run_peak(variants=(0, 1, 2, 3))}), flush=True)
         return
     if a.consumer_alone:
         from paper_1603_06958_amd import inputs

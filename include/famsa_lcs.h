@@ -385,6 +385,32 @@ void famsa_lcs_server_destroy(famsa_lcs_server_t* srv);
  * ------------------------------------------------------------------------ */
 int famsa_lcs_autotune(famsa_lcs_plan_t* plan, const char* cache_path);
 
+/* ------------------------------------------------------------------------
+ * Integer-VALU ceiling (Methods, "Pairwise similarities calculation": the
+ * bit-parallel step costs O(|A||B|/w); on gfx950 it is three 32-bit VALU
+ * instructions per 32 cells).  Runs long register-only chains of exactly
+ * those instructions on every CU and reports their rate and the shader
+ * clock measured inside the kernel (s_memtime over s_memrealtime).
+ *   variant        0 the recurrence (v_and_b32, v_addc_co_u32 chained over 8
+ *                  dwords, v_bitop3_b32), 1 v_and_b32 only, 2 v_addc_co_u32
+ *                  only, 3 v_bitop3_b32 only
+ *   blocks_per_cu  workgroups of 256 threads per CU (1..32)
+ *   iters          loop iterations, 192 instructions per lane each (1..2^24)
+ * Errors: EINVAL (bad argument), EDEVICE (no GPU or a HIP failure).
+ * ------------------------------------------------------------------------ */
+typedef struct famsa_valu_peak_result {
+  double ms;                       /* event-timed kernel duration */
+  double lane_ops;                 /* 32-bit lane operations executed */
+  double ops_per_s;                /* lane_ops / duration */
+  double clock_ghz;                /* mean shader clock over the workgroups' loops */
+  double mean_loop_cycles;         /* mean shader-clock cycles of a workgroup's loop */
+  double lane_ops_per_clk_per_cu;  /* ops_per_s / (clock * CUs) */
+  uint32_t cus;
+} famsa_valu_peak_result;
+
+int famsa_valu_peak(int device, uint32_t variant, uint32_t blocks_per_cu, uint32_t iters,
+                    famsa_valu_peak_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,12 @@ class Stats(ctypes.Structure):
                 ("wall_ms", ctypes.c_double), ("tiles", ctypes.c_uint64)]
 
 
+class PeakResult(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("lane_ops", ctypes.c_double), ("ops_per_s", ctypes.c_double),
+                ("clock_ghz", ctypes.c_double), ("mean_loop_cycles", ctypes.c_double),
+                ("lane_ops_per_clk_per_cu", ctypes.c_double), ("cus", ctypes.c_uint32)]
+
+
 TILE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(Tile))
 
 _lib = None
@@ -153,8 +159,19 @@ def lib():
         L.famsa_lcs_server_memory.restype = ctypes.c_int
         L.famsa_lcs_server_destroy.argtypes = [vp]
         L.famsa_lcs_server_destroy.restype = None
+        L.famsa_valu_peak.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.POINTER(PeakResult)]
+        L.famsa_valu_peak.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def valu_peak(variant: int = 0, blocks_per_cu: int = 8, iters: int = 20000, device: int = 0) -> PeakResult:
+    """Rate of register-only chains of the LCS step's VALU instructions
+    (famsa_valu_peak): variant 0 the recurrence, 1 AND, 2 ADDC, 3 BITOP3."""
+    r = PeakResult()
+    check(lib().famsa_valu_peak(device, variant, blocks_per_cu, iters, ctypes.byref(r)))
+    return r
 
 
 def last_error() -> str:

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfamsa_lcs.so")
-SOURCES = ["lcs_kernels.hip", "mst.hip", "gapped.hip", "runtime.cpp", "plan.cpp", "autotune.cpp", "slink.cpp", "server.cpp", "guide_tree.cpp"]
+SOURCES = ["lcs_kernels.hip", "mst.hip", "gapped.hip", "peak.hip", "runtime.cpp", "plan.cpp", "autotune.cpp", "slink.cpp", "server.cpp", "guide_tree.cpp"]
 ARCH = os.environ.get("FAMSA_LCS_ARCH", "gfx950")
 
 
@@ -20,30 +20,33 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library; returns its path."""
+def _compile(src: str, objdir: str, common, verbose: bool) -> str:
+    path = os.path.join(CSRC, src)
+    if not os.path.exists(path):
+        raise RuntimeError("missing source: " + path)
+    obj = os.path.join(objdir, src + ".o")
+    cmd = [hipcc(), "-c", path, "-o", obj] + common + ["--offload-arch=" + ARCH]
+    if src.endswith(".hip"):  # device code: HIP for gfx950
+        cmd += ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("compile failed: " + src)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel) and link the shared library; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
               "-I" + os.path.join(HERE, "..", "include")]
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        if not os.path.exists(path):
-            continue
-        obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc(), "-c", path, "-o", obj] + common
-        if src.endswith(".hip"):  # device code: HIP for gfx950
-            cmd += ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-        else:  # host code calling the HIP runtime
-            cmd += ["--offload-arch=" + ARCH]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError("compile failed: " + src)
-        objs.append(obj)
+    jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda src: _compile(src, objdir, common, verbose), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-o", tmp] + objs + ["--offload-arch=" + ARCH]
     r = subprocess.run(cmd, capture_output=True, text=True)

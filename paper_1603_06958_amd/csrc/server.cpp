@@ -45,7 +45,10 @@ struct Job {
   bool whole = false;           // the whole triangle goes in one step
   uint64_t remaining_cells = 0;
   std::vector<uint64_t> tile_cells;
+  uint32_t bypassed = 0;        // jobs admitted while this one was the oldest queued
 };
+
+constexpr uint32_t kMaxBypass = 64;
 
 struct StepTile {
   Job* job;
@@ -111,10 +114,19 @@ struct famsa_lcs_server_s {
   int deliver(int si, famsa_lcs_tile_fn fn, void* user);
 };
 
+// Admission: every queued job whose footprint fits what the budget has left
+// is admitted, oldest first; a job that does not fit stays queued and later
+// (smaller) jobs may pass it.  So that a large job is not passed forever, once
+// kMaxBypass jobs have been admitted past the oldest queued job, nothing more
+// is admitted until that one fits.
 int famsa_lcs_server_s::admit() {
-  while (!queue.empty()) {
-    Job* j = queue.front();
-    if (in_use + j->footprint > budget - fixed) break;  // first come, first admitted
+  for (auto it = queue.begin(); it != queue.end();) {
+    Job* j = *it;
+    if (in_use + j->footprint > budget - fixed) {
+      if (queue.front()->bypassed >= kMaxBypass) break;
+      ++it;
+      continue;
+    }
     j->dev.reset(new DeviceBatchOwner());
     int rc = j->dev->create(j->codes.data(), j->off.data(), j->k, opt.sigma, cs);
     if (rc) return rc;
@@ -123,7 +135,8 @@ int famsa_lcs_server_s::admit() {
     j->state = 1;
     std::vector<uint8_t>().swap(j->codes);
     active.push_back(j);
-    queue.pop_front();
+    if (it != queue.begin()) ++queue.front()->bypassed;
+    it = queue.erase(it);
   }
   return 0;
 }

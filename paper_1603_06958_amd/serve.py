@@ -92,9 +92,11 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
     done_t: Dict[int, float] = {}
     submit_t: Dict[int, float] = {}
     tile_rows = server_opts.get("tile_rows", 1024)
+    step_jobs: List[set] = []  # job ids whose tiles each step call delivered
 
     def fn(t):
         j = int(t.family)
+        step_jobs[-1].add(j)
         if on_tile:
             on_tile(j, t)
         tiles_left[j] -= 1
@@ -122,8 +124,10 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
             wait = jobs[order[nxt]].arrival_s - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.05))
+            step_jobs.append(set())
             active = srv.step(fn)
             continue
+        step_jobs.append(set())
         active = srv.step(fn)
     wall = time.perf_counter() - t0
     mem = srv.memory()
@@ -134,7 +138,8 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
     return {"jobs": n, "wall_s": round(wall, 3), "pairs_per_s": round(pairs / wall, 1),
             "gcups": round(cells / wall / 1e9, 1), "p50_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_ms": round(float(np.percentile(lat, 99)), 2), "max_ms": round(float(lat.max()), 2),
-            "peak_device_bytes": mem[1], "latencies_ms": lat, "job_ids": ids}
+            "peak_device_bytes": mem[1], "latencies_ms": lat, "job_ids": ids,
+            "max_jobs_per_step": max((len(x) for x in step_jobs), default=0), "step_jobs": step_jobs}
 
 
 # Serving steps are kept small so that a new job waits for little work ahead of

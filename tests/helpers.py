@@ -43,6 +43,16 @@ def check_all_tiles(b, tiles, tile_rows):
                                  f"got {got[p]} want {exp[p]}")
 
 
+def digest(a: np.ndarray) -> bytes:
+    """128-bit digest of an array's bytes (xxh3 when available, else blake2b)."""
+    try:
+        import xxhash
+        return xxhash.xxh3_128_digest(np.ascontiguousarray(a).view(np.uint8))
+    except ImportError:
+        import hashlib
+        return hashlib.blake2b(np.ascontiguousarray(a).tobytes(), digest_size=16).digest()
+
+
 class Sampler:
     """Tile callback keeping `per_tile` seeded samples (and bound checks)."""
 
@@ -73,11 +83,15 @@ class Sampler:
             for a, c, v in zip(i, j, vals[pos]):
                 self.samples.append((base + int(a), base + int(c), int(v)))
             if self.ntiles % self.every == 0:
-                ii, jj = np.repeat(rows, k - 1 - rows), None
-                # 0 <= LCS <= min(|A_i|, |A_j|)
-                jj = np.concatenate([np.arange(x + 1, k) for x in rows]) if rows.size else np.zeros(0, np.int64)
-                mn = np.minimum(self.L[base + ii], self.L[base + jj])
-                assert (vals >= 0).all() and (vals <= mn).all(), "LCS outside [0, min length]"
+                # 0 <= LCS <= min(|A_i|, |A_j|) over every value of the tile
+                assert (vals >= 0).all(), "negative LCS"
+                Lf = self.L[base:base + k]
+                p = 0
+                for i in range(r0, r1):
+                    n = k - 1 - i
+                    if n and (vals[p:p + n] > np.minimum(Lf[i], Lf[i + 1:])).any():
+                        raise AssertionError(f"LCS above the shorter length in row {i} of family {f}")
+                    p += n
         self.ntiles += 1
         return 0
 

@@ -137,3 +137,12 @@ def test_no_gpu_is_edevice():
         pass
     rc, msg = plan_rc([0, 1, 2], [0, 3])
     assert rc == B.EDEVICE, msg
+
+
+def test_valu_peak_rejects_bad_arguments():
+    L = B.lib()
+    r = B.PeakResult()
+    assert L.famsa_valu_peak(0, 4, 8, 100, ctypes.byref(r)) == B.EINVAL
+    assert L.famsa_valu_peak(0, 0, 0, 100, ctypes.byref(r)) == B.EINVAL
+    assert L.famsa_valu_peak(0, 0, 8, 0, ctypes.byref(r)) == B.EINVAL
+    assert L.famsa_valu_peak(0, 0, 8, 100, None) == B.EINVAL

@@ -1,14 +1,18 @@
 """Full-size workloads, in the launch configurations bench.py times (c2, c3,
 c4, and the c5 serving jobs): seeded samples of every tile checked against
-the oracle one pair at a time, plus 0 <= LCS <= min(|A|, |B|) over whole
-tiles; on c2 and c3 every value of the batched kernels also equals the
-plain kernel's."""
-import hashlib
+the oracle one pair at a time, plus 0 <= LCS <= min(|A|, |B|) over every
+value of every tile; every value of the batched kernels also equals the
+plain kernel's (c2, c3, c4: per-tile digests), and every c5 job's tiles are
+the same in the serving mix as when the job runs alone; on c4 the host
+SLINK consumer and the GPU spanning-tree consumer, both fed the GPU's tiles,
+give the same merge heights, and every tree edge's LCS is the oracle's."""
+from fractions import Fraction
 
 import numpy as np
 import pytest
 
-from helpers import Sampler, check_all_tiles
+import oracle
+from helpers import Sampler, check_all_tiles, digest
 from paper_1603_06958_amd import binding as B
 from paper_1603_06958_amd import inputs
 
@@ -21,7 +25,7 @@ def run_hashed(b, sampler=None, **opt):
 
     def fn(t):
         a = B.tile_array(t)
-        out[(int(t.family), int(t.row_begin), int(t.row_end))] = hashlib.blake2b(a.tobytes(), digest_size=16).digest()
+        out[(int(t.family), int(t.row_begin), int(t.row_end))] = digest(a)
         return sampler(t) if sampler else 0
 
     with B.Plan.from_batch(b, **opt) as p:
@@ -44,43 +48,100 @@ def test_sampled_and_batched_equals_plain(name, seed, per_tile):
     assert all(plain[key] == batched[key] for key in batched)
 
 
-@pytest.mark.timeout(600)
-def test_c4_sampled_bench_configuration():
-    # the launch configuration bench.py times: 2^28-value steps on one
-    # compute stream, direct launches, autotuned launch shape
+@pytest.fixture(scope="module")
+def c4_plain():
+    """c4 and the plain kernel's per-tile digests (one pass, ~12 s)."""
     b = inputs.c4()
-    s = Sampler(b, per_tile=60, seed=3, bound_check_every=25)
+    return b, run_hashed(b, flags=B.PLAIN)
+
+
+@pytest.mark.timeout(900)
+def test_c4_bench_configuration_every_tile_equals_plain(c4_plain):
+    # the launch configuration bench.py times: 2^28-value steps on one
+    # compute stream, direct launches, autotuned launch shape; every one of
+    # the 98 tiles (5.0e9 values) equals the plain kernel's by digest and is
+    # within [0, min length]; 60 seeded values per tile match the oracle
+    b, plain = c4_plain
+    s = Sampler(b, per_tile=60, seed=3)
+    batched = {}
+
+    def fn(t):
+        batched[(int(t.family), int(t.row_begin), int(t.row_end))] = digest(B.tile_array(t))
+        return s(t)
+
     with B.Plan.from_batch(b, flags=B.ONE_STREAM | B.NO_GRAPH, step_values=1 << 28) as p:
         p.autotune(None)
-        p.run(s)
+        p.run(fn)
     assert s.ntiles == 98
     assert s.count == b.pairs()
     assert s.check() >= 5000
+    assert plain.keys() == batched.keys() and len(plain) == 98
+    bad = [key for key in batched if plain[key] != batched[key]]
+    assert not bad, f"{len(bad)} tiles differ from the plain kernel, first {bad[0]}"
+
+
+def _sim_key(n, d):
+    return oracle.INF if d == 0 else Fraction(int(n), int(d))
+
+
+@pytest.mark.timeout(900)
+def test_c4_host_slink_heights_equal_gpu_tree():
+    # stage II at the headline scale: the host SLINK over all 98 descending
+    # host tiles and the GPU spanning-forest consumer over device tiles give
+    # the same multiset of 99,999 merge similarities; the GPU tree's edges
+    # carry the oracle's LCS of their pairs
+    b = inputs.c4()
+    k = b.nseq
+    s = B.SLink(b.lengths())
+    with B.Plan.from_batch(b, flags=B.DESCENDING, step_values=1 << 28) as p:
+        p.run_native(B.SLink.consume_fn(), s.handle)
+    pi, num, den = s.result()
+    s.close()
+    m = B.Mst(b.lengths())
+    with B.Plan.from_batch(b, flags=B.DEVICE_TILES, step_values=1 << 28) as p:
+        p.run_native(B.Mst.consume_fn(), m.handle)
+    u, v, L, D = m.result()
+    m.close()
+    assert len(u) == k - 1
+    slink_h = sorted(_sim_key(n, q) for n, q in zip(num, den) if not (n == -1 and q == 0))
+    assert len(slink_h) == k - 1
+    assert sorted(_sim_key(x, y) for x, y in zip(L, D)) == slink_h
+    exp = oracle.lcs_pairs(b.codes, b.seq_off, u.astype(np.int64), v.astype(np.int64))
+    assert np.array_equal(exp, np.asarray(L, dtype=np.int64))
+    lens = b.lengths().astype(np.int64)
+    d = lens[u] + lens[v] - 2 * exp
+    assert np.array_equal(d * d, np.asarray(D, dtype=np.int64))
 
 
 @pytest.mark.timeout(600)
-def test_c4_sampled_two_streams_with_graphs():
-    # graph replays alternating between two compute streams
-    b = inputs.c4()
-    s = Sampler(b, per_tile=20, seed=4, bound_check_every=49)
-    with B.Plan.from_batch(b, flags=B.TWO_STREAMS) as p:
-        p.run(s)
+def test_c4_two_streams_with_graphs_equals_plain(c4_plain):
+    # graph replays alternating between two compute streams: every tile
+    # equals the plain kernel's, and seeded samples match the oracle
+    b, plain = c4_plain
+    s = Sampler(b, per_tile=20, seed=4)
+    got = run_hashed(b, sampler=s, flags=B.TWO_STREAMS)
     assert s.ntiles == 98 and s.count == b.pairs()
     s.check()
+    assert got == plain
 
 
 def test_c5_jobs_sampled_in_the_serving_configuration():
     # every job of the serving workload through the server as bench.py runs
-    # it (2^24-value, 2^41-cell steps, 256-row tiles), arrivals replayed at once
+    # it (2^24-value, 2^41-cell steps, 256-row tiles), arrivals replayed at
+    # once; every tile of every job equals the job's tile when it runs alone
+    # (digests), seeded samples match the oracle and every value is within
+    # [0, min length]
     from paper_1603_06958_amd import serve
-    jobs = inputs.c5(seed=4, njobs=40, rate_per_s=serve.C5_RATE_PER_S)  # the bench's 40 jobs
+    jobs = inputs.c5(seed=4, njobs=40, rate_per_s=serve.C5_RATE_PER_S)  # the first 40 jobs of the bench's mix
     samplers = {}
+    mixed = {}
 
     def on_tile(jid, t):
         if jid not in samplers:
-            samplers[jid] = Sampler(jobs[r_ids[jid]].batch, per_tile=30, seed=jid, bound_check_every=7)
+            samplers[jid] = Sampler(jobs[r_ids[jid]].batch, per_tile=30, seed=jid)
         local = B.Tile.from_buffer_copy(t)  # the job's own batch holds one family
         local.family = 0
+        mixed[(jid, int(t.row_begin), int(t.row_end))] = digest(B.tile_array(t))
         samplers[jid](local)
 
     r_ids = {}
@@ -89,12 +150,21 @@ def test_c5_jobs_sampled_in_the_serving_configuration():
     for i, j in enumerate(jobs):
         r_ids[srv.submit(j.batch.codes, j.batch.seq_off)] = i
     active = 1
+    per_step = []
     while active:
-        active = srv.step(lambda t: on_tile(int(t.family), t))
+        seen = set()
+        active = srv.step(lambda t: (seen.add(int(t.family)), on_tile(int(t.family), t))[1])
+        per_step.append(seen)
     srv.close()
+    assert max(len(x) for x in per_step) >= 2  # tiles of several jobs in one step
     assert len(samplers) == len(jobs)
     total = 0
     for jid, smp in samplers.items():
         assert smp.count == jobs[r_ids[jid]].batch.pairs()
         total += smp.check()
     assert total >= 1000
+    # each job alone, through a plan with the same tile rows
+    for jid, i in r_ids.items():
+        alone = run_hashed(jobs[i].batch, tile_rows=serve.SERVE_TILE_ROWS)
+        for (f, r0, r1), h in alone.items():
+            assert mixed[(jid, r0, r1)] == h, (jid, r0)

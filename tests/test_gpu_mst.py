@@ -107,9 +107,30 @@ def test_tree_matches_oracle(seed, k, lo, hi, sigma, R, flags):
     assert (cophenetic_from_tree(k, got) == c_ref).all()
 
 
+@pytest.mark.parametrize("seed,k,R,sigma", [(8, 700, 100, 20), (9, 640, 300, 3)])
+def test_tree_matches_oracle_many_blocks(seed, k, R, sigma):
+    # several 256-column scan blocks and 64-row slices per tile, tiles whose
+    # first row is past column 255 (scan blocks before it skipped), and ties:
+    # identical and empty sequences, and a small alphabet
+    b = inputs.random_family(k, 0, 90, seed, alphabet=sigma)
+    seqs = [b.seq(i) for i in range(k)]
+    for a, c in ((5, 300), (301, 300), (600, 2), (650, 2), (299, 298)):
+        seqs[a] = seqs[c].copy()
+    for e in (7, 400, 401, k - 1):
+        seqs[e] = np.zeros(0, np.uint8)
+    b = inputs.from_sequences(seqs)
+    M = oracle.full_matrix(b.codes, b.seq_off, 0, k)
+    L = b.lengths()
+    u, v, l, d, gt = gpu_tree(b, True, tile_rows=R, alphabet_size=max(sigma, 2))
+    assert len(u) == k - 1
+    got = sorted((int(a), int(c), sim(x, y)) for a, c, x, y in zip(u, v, l, d))
+    assert got == sorted(oracle_tree(M, L))
+    assert [(int(a), int(c), sim(x, y)) for a, c, x, y in zip(*gt)] == oracle.guide_tree(M, L)
+
+
 @pytest.mark.parametrize("k,R", [(3000, 256), (9000, 700)])
 def test_heights_match_host_slink_c2_like(k, R):
-    # k = 9000 spans three 4096-column chunks of the row pass
+    # k = 9000: tiles of 700 rows across 36 column blocks of 256
     b = inputs.c2(k=k)
     u, v, l, d = gpu_tree(b, tile_rows=R, step_values=2_000_000)
     s = B.SLink(b.lengths())

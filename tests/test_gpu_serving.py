@@ -33,11 +33,21 @@ def collect(jobs, **opt):
     return got, r
 
 
-@pytest.mark.parametrize("R,step_values,step_cells", [(64, 0, 0), (16, 5000, 0), (32, 0, 3_000_000)])
-def test_serving_matches_oracle_and_alone(R, step_values, step_cells):
+@pytest.mark.parametrize("R,step_values,step_cells,realtime", [
+    (64, 0, 0, True), (16, 5000, 0, True), (32, 0, 3_000_000, True),
+    (64, 0, 0, False), (16, 5000, 0, False), (32, 0, 3_000_000, False)])
+def test_serving_matches_oracle_and_alone(R, step_values, step_cells, realtime):
     jobs = small_jobs()
-    got, r = collect(jobs, tile_rows=R, step_values=step_values, step_cells=step_cells)
+    got, r = collect(jobs, tile_rows=R, step_values=step_values, step_cells=step_cells, realtime=realtime)
     ids = r["job_ids"]
+    if not realtime and step_cells == 0:
+        # every job queued before the first step and steps bounded by values
+        # only: steps must hold tiles of several jobs at once, so the
+        # comparison below is of results computed in a mix (a 3e6-cell bound
+        # lets one tile of these jobs fill a step)
+        assert r["max_jobs_per_step"] >= 2
+        mixed = [s for s in r["step_jobs"] if len(s) >= 2]
+        assert len(set().union(*mixed)) >= 2
     for jid, i in ids.items():
         b = jobs[i].batch
         k = b.nseq
@@ -78,3 +88,47 @@ def test_alone_service_times():
     jobs = small_jobs(4, seed=8)
     t = serve.alone_ms(jobs, tile_rows=64)
     assert t.shape == (4,) and (t > 0).all() and np.isfinite(t).all()
+
+
+def test_admission_passes_a_job_that_does_not_fit_yet():
+    # A holds most of the budget; B fits alone but not beside A; C fits
+    # beside A.  C is admitted on the first step although B is older, and B
+    # once A has finished; every result still equals the oracle.
+    A = inputs.random_family(200, 250, 350, 31)
+    Bj = inputs.random_family(150, 250, 350, 32)
+    C = inputs.random_family(20, 40, 60, 33)
+    sv = 1 << 16
+
+    def footprint(b):
+        srv = serve.Server(step_values=sv, tile_rows=64)
+        fixed = srv.memory()[0]
+        srv.submit(b.codes, b.seq_off)
+        srv.step(None)
+        used = srv.memory()[0]
+        while srv.step(None):
+            pass
+        srv.close()
+        return fixed, used - fixed
+
+    fixed, fA = footprint(A)
+    _, fB = footprint(Bj)
+    _, fC = footprint(C)
+    assert fC + 100 < fB <= fA + fC
+    srv = serve.Server(step_values=sv, tile_rows=64, hbm_budget=fixed + fA + fC + 100)
+    got = {}
+    ids = [srv.submit(b.codes, b.seq_off) for b in (A, Bj, C)]
+
+    def keep(t):
+        got[(int(t.family), int(t.row_begin), int(t.row_end))] = B.tile_array(t).copy()
+        return 0
+
+    active = srv.step(keep)
+    assert [srv.job_state(j) for j in ids] == [1, 0, 1]
+    while active:
+        active = srv.step(keep)
+    srv.close()
+    for jid, b in zip(ids, (A, Bj, C)):
+        k = b.nseq
+        for r0 in range(0, k, 64):
+            r1 = min(k, r0 + 64)
+            assert np.array_equal(got[(jid, r0, r1)], oracle.tile_expected(b.codes, b.seq_off, 0, k, r0, r1))
