@@ -114,7 +114,7 @@ def test_tree_matches_oracle_many_blocks(seed, k, R, sigma):
     # identical and empty sequences, and a small alphabet
     b = inputs.random_family(k, 0, 90, seed, alphabet=sigma)
     seqs = [b.seq(i) for i in range(k)]
-    for a, c in ((5, 300), (301, 300), (600, 2), (650, 2), (299, 298)):
+    for a, c in ((5, 300), (301, 300), (600, 2), (630, 2), (299, 298)):
         seqs[a] = seqs[c].copy()
     for e in (7, 400, 401, k - 1):
         seqs[e] = np.zeros(0, np.uint8)
