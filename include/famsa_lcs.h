@@ -411,6 +411,40 @@ typedef struct famsa_valu_peak_result {
 int famsa_valu_peak(int device, uint32_t variant, uint32_t blocks_per_cu, uint32_t iters,
                     famsa_valu_peak_result* out);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the LCS of every pair
+ * i < j of one family, the values famsa_lcs_plan + famsa_lcs_tiles give for
+ * a single tile of all rows, computed with no allocation of any kind.  Its
+ * working memory is one static device array per GPU of
+ * FAMSA_LCS_NOALLOC_SCRATCH_BYTES (about 32 MiB), held from the library's
+ * first use of that GPU until the process ends; planning runs on the device.
+ *   codes      DEVICE pointer: sequence i is codes[seq_off[i] .. seq_off[i+1])
+ *   seq_off    DEVICE pointer: nseq + 1 offsets
+ *   nseq       <= FAMSA_LCS_NOALLOC_MAX_SEQ
+ *   out        DEVICE pointer: nseq (nseq - 1) / 2 int32, row-major upper
+ *              triangle, LCS(i, j) at i nseq - i (i + 1) / 2 + (j - i - 1)
+ *   status     DEVICE pointer to one int32 or NULL: 0 when every value was
+ *              computed, FAMSA_LCS_EINVAL when the device found the input
+ *              invalid (decreasing offsets, a length over the limit below, a
+ *              code >= alphabet_size); then every value of out is -1
+ *   device     HIP ordinal; stream: hipStream_t or NULL.  The work is queued
+ *              on the stream and the call returns without waiting.
+ * Limits: lengths <= FAMSA_LCS_NOALLOC_MAX_LEN for alphabet_size <= 20,
+ * <= FAMSA_LCS_NOALLOC_MAX_LEN_S32 for alphabet_size 21..32.
+ * Calls on one GPU share its array: two calls whose work overlaps on the
+ * device (different streams, or different host threads) race and give wrong
+ * results; calls ordered on one stream are safe.
+ * Errors (returned, nothing queued): EINVAL (alphabet_size, nseq over the
+ * limit, NULL pointer, bad device), EDEVICE (a HIP call failed).
+ * ------------------------------------------------------------------------ */
+#define FAMSA_LCS_NOALLOC_MAX_SEQ 8192u
+#define FAMSA_LCS_NOALLOC_MAX_LEN 896u
+#define FAMSA_LCS_NOALLOC_MAX_LEN_S32 512u
+#define FAMSA_LCS_NOALLOC_SCRATCH_BYTES 33755392u
+int famsa_lcs_family_noalloc(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
+                             uint32_t alphabet_size, int32_t* out, int32_t* status, int device, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -162,6 +162,8 @@ def lib():
         L.famsa_valu_peak.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.POINTER(PeakResult)]
         L.famsa_valu_peak.restype = ctypes.c_int
+        L.famsa_lcs_family_noalloc.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp, vp, ctypes.c_int, vp]
+        L.famsa_lcs_family_noalloc.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -172,6 +174,19 @@ def valu_peak(variant: int = 0, blocks_per_cu: int = 8, iters: int = 20000, devi
     r = PeakResult()
     check(lib().famsa_valu_peak(device, variant, blocks_per_cu, iters, ctypes.byref(r)))
     return r
+
+
+NOALLOC_MAX_SEQ, NOALLOC_MAX_LEN, NOALLOC_MAX_LEN_S32 = 8192, 896, 512
+
+
+def family_noalloc(codes_ptr: int, seq_off_ptr: int, nseq: int, out_ptr: int, status_ptr: Optional[int] = None,
+                   alphabet_size: int = 20, device: int = 0, stream: Optional[int] = None) -> None:
+    """famsa_lcs_family_noalloc on device buffers given by address (for
+    example torch tensors' data_ptr()): codes uint8, seq_off uint64 (nseq + 1),
+    out int32 (nseq (nseq - 1) / 2), status one int32 or None.  Queued on
+    `stream`; returns without waiting."""
+    check(lib().famsa_lcs_family_noalloc(codes_ptr or None, seq_off_ptr or None, nseq, alphabet_size,
+                                         out_ptr or None, status_ptr or None, device, stream))
 
 
 def last_error() -> str:

@@ -146,3 +146,15 @@ def test_valu_peak_rejects_bad_arguments():
     assert L.famsa_valu_peak(0, 0, 0, 100, ctypes.byref(r)) == B.EINVAL
     assert L.famsa_valu_peak(0, 0, 8, 0, ctypes.byref(r)) == B.EINVAL
     assert L.famsa_valu_peak(0, 0, 8, 100, None) == B.EINVAL
+
+
+def test_noalloc_rejects_on_the_host():
+    # the allocation-free entry point checks its sizes before any HIP call
+    L = B.lib()
+    assert L.famsa_lcs_family_noalloc(1, 1, B.NOALLOC_MAX_SEQ + 1, 20, 1, None, 0, None) == B.EINVAL
+    assert "scratch" in B.last_error()
+    assert L.famsa_lcs_family_noalloc(1, 1, 10, 0, 1, None, 0, None) == B.EINVAL
+    assert L.famsa_lcs_family_noalloc(1, None, 10, 20, 1, None, 0, None) == B.EINVAL
+    assert L.famsa_lcs_family_noalloc(1, 1, 10, 20, None, None, 0, None) == B.EINVAL
+    assert L.famsa_lcs_family_noalloc(1, 1, 10, 20, 1, None, -1, None) == B.EINVAL
+
