@@ -412,6 +412,59 @@ int famsa_valu_peak(int device, uint32_t variant, uint32_t blocks_per_cu, uint32
                     famsa_valu_peak_result* out);
 
 /* ------------------------------------------------------------------------
+ * Aligning one sequence to a profile: the specialised DP the progressive
+ * stage runs when one side of a merge is a single sequence (Methods,
+ * "Progressive construction of the alignment"), with affine terminal and
+ * non-terminal gap costs and gap-type corrections ("Gap types and costs
+ * determination").  A batch of independent problems (one level of the guide
+ * tree) runs in one call.  Problem p:
+ *   sequence   seqs[seq_off[p] .. seq_off[p+1]), m codes < alphabet_size
+ *   profile    nrows[p] >= 1 gapped rows of width[p] columns, row-major at
+ *              rows + rows_off[p]; each byte a code < alphabet_size or
+ *              FAMSA_PROFILE_GAP
+ *   subst      alphabet_size x alphabet_size scores, S[x][a] at
+ *              subst[x * alphabet_size + a]; |S| <= FAMSA_PROFILE_MAX_SUBST
+ *   gap_costs  To, Te, Go, Ge (terminal open, terminal extension, open,
+ *              extension), already scaled (famsa_gap_costs_scaled);
+ *              |cost| <= FAMSA_PROFILE_MAX_GAP
+ * The score of an alignment sums, over the profile's rows, the pair score
+ * with the sequence: S[x][a] where residue a faces residue x; a gap run in
+ * the sequence against columns costs each column's residue count times To
+ * or Go for the first column and Te or Ge for the rest (terminal before
+ * the first and after the last residue); a run of new gap columns inserted
+ * into the profile at a boundary costs each row, for the first column, Te
+ * or To in its terminal region (next to a gap or opening) and Ge or Go
+ * inside, and Te or Ge for the others.  The DP maximises it; among optimal
+ * alignments it returns the one that prefers, at every cell, M over D over
+ * I (the first maximum in that order).
+ * Outputs: score[p]; ops + ops_off[p] (room for m + width[p] bytes) gets
+ * the alignment from its first column: FAMSA_PROFILE_OP_M residue against
+ * column, _D column against a gap in the sequence, _I residue against a new
+ * gap column; nops[p] its length.  Synchronous; inputs are host memory.
+ * Errors: EINVAL (bad argument), ENOMEM, EDEVICE.
+ * ------------------------------------------------------------------------ */
+#define FAMSA_PROFILE_GAP 0xFFu
+#define FAMSA_PROFILE_OP_M 0u
+#define FAMSA_PROFILE_OP_D 1u
+#define FAMSA_PROFILE_OP_I 2u
+#define FAMSA_PROFILE_MAX_PROBLEMS (1u << 20)
+#define FAMSA_PROFILE_MAX_ROWS (1u << 20)
+#define FAMSA_PROFILE_MAX_SUBST 1024u
+#define FAMSA_PROFILE_MAX_GAP (1u << 20)
+int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const uint64_t* seq_off, const uint8_t* rows,
+                        const uint64_t* rows_off, const uint32_t* nrows, const uint32_t* width,
+                        uint32_t alphabet_size, const int32_t* subst, const int64_t* gap_costs, int device,
+                        int64_t* score, uint8_t* ops, const uint64_t* ops_off, uint32_t* nops);
+/* Duration in ms (HIP events) of the DP launch of the last famsa_profile_align
+ * call in this process. */
+double famsa_profile_last_dp_ms(void);
+/* The gap costs scaled by the family size (same section): every cost times
+ * g_scale = 1 + ln(k / gl) / gd (the paper's defaults gl = 45, gd = 7),
+ * rounded to the nearest integer, halves away from zero.
+ * Errors: EINVAL (k = 0, gl <= 0, gd = 0, a result beyond FAMSA_PROFILE_MAX_GAP). */
+int famsa_gap_costs_scaled(uint32_t k, const double* base, double gl, double gd, int64_t* out);
+
+/* ------------------------------------------------------------------------
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the LCS of every pair
  * i < j of one family, the values famsa_lcs_plan + famsa_lcs_tiles give for

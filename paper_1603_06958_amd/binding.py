@@ -164,6 +164,14 @@ def lib():
         L.famsa_valu_peak.restype = ctypes.c_int
         L.famsa_lcs_family_noalloc.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp, vp, ctypes.c_int, vp]
         L.famsa_lcs_family_noalloc.restype = ctypes.c_int
+        L.famsa_profile_align.argtypes = [ctypes.c_uint32, u8p, u64p, u8p, u64p, u32p, u32p, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_int32), i64p, ctypes.c_int, i64p, u8p, u64p, u32p]
+        L.famsa_profile_align.restype = ctypes.c_int
+        L.famsa_profile_last_dp_ms.argtypes = []
+        L.famsa_profile_last_dp_ms.restype = ctypes.c_double
+        L.famsa_gap_costs_scaled.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                             ctypes.c_double, i64p]
+        L.famsa_gap_costs_scaled.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -187,6 +195,54 @@ def family_noalloc(codes_ptr: int, seq_off_ptr: int, nseq: int, out_ptr: int, st
     `stream`; returns without waiting."""
     check(lib().famsa_lcs_family_noalloc(codes_ptr or None, seq_off_ptr or None, nseq, alphabet_size,
                                          out_ptr or None, status_ptr or None, device, stream))
+
+
+PROFILE_GAP = 0xFF
+OP_M, OP_D, OP_I = 0, 1, 2
+
+
+def profile_align(problems, subst, gap_costs, alphabet_size: Optional[int] = None, device: int = 0):
+    """famsa_profile_align over a list of (sequence, rows) pairs: sequence
+    uint8 codes, rows a K x n uint8 array (PROFILE_GAP for gaps).  Returns
+    (scores int64 array, list of op arrays)."""
+    S = np.ascontiguousarray(subst, dtype=np.int32)
+    sigma = int(S.shape[0]) if alphabet_size is None else alphabet_size
+    seqs = [np.ascontiguousarray(a, dtype=np.uint8).reshape(-1) for a, _ in problems]
+    rows = [np.ascontiguousarray(r, dtype=np.uint8) for _, r in problems]
+    n = len(seqs)
+    seq_off = np.zeros(n + 1, np.uint64)
+    np.cumsum([x.size for x in seqs], out=seq_off[1:])
+    rows_off = np.zeros(n + 1, np.uint64)
+    np.cumsum([r.size for r in rows], out=rows_off[1:])
+    nrows = np.array([r.shape[0] for r in rows], np.uint32)
+    width = np.array([r.shape[1] for r in rows], np.uint32)
+    ops_off = np.zeros(n + 1, np.uint64)
+    np.cumsum([x.size + r.shape[1] for x, r in zip(seqs, rows)], out=ops_off[1:])
+    cat_s = np.concatenate(seqs) if n and int(seq_off[-1]) else np.zeros(1, np.uint8)
+    cat_r = np.concatenate([r.reshape(-1) for r in rows]) if n and int(rows_off[-1]) else np.zeros(1, np.uint8)
+    costs = np.ascontiguousarray(gap_costs, dtype=np.int64)
+    score = np.zeros(max(n, 1), np.int64)
+    ops = np.zeros(max(int(ops_off[-1]), 1), np.uint8)
+    nops = np.zeros(max(n, 1), np.uint32)
+    check(lib().famsa_profile_align(n, _ptr(cat_s, ctypes.c_uint8), _ptr(seq_off, ctypes.c_uint64),
+                                    _ptr(cat_r, ctypes.c_uint8), _ptr(rows_off, ctypes.c_uint64),
+                                    _ptr(nrows, ctypes.c_uint32), _ptr(width, ctypes.c_uint32), sigma,
+                                    _ptr(S, ctypes.c_int32), _ptr(costs, ctypes.c_int64), device,
+                                    _ptr(score, ctypes.c_int64), _ptr(ops, ctypes.c_uint8),
+                                    _ptr(ops_off, ctypes.c_uint64), _ptr(nops, ctypes.c_uint32)))
+    return score[:n], [ops[int(ops_off[p]):int(ops_off[p]) + int(nops[p])].copy() for p in range(n)]
+
+
+def profile_last_dp_ms() -> float:
+    return float(lib().famsa_profile_last_dp_ms())
+
+
+def gap_costs_scaled(k: int, base, gl: float = 45.0, gd: float = 7.0) -> Tuple[int, int, int, int]:
+    """(To, Te, Go, Ge) scaled by 1 + ln(k / gl) / gd and rounded (famsa_gap_costs_scaled)."""
+    b = np.ascontiguousarray(base, dtype=np.float64)
+    out = np.zeros(4, np.int64)
+    check(lib().famsa_gap_costs_scaled(k, _ptr(b, ctypes.c_double), gl, gd, _ptr(out, ctypes.c_int64)))
+    return tuple(int(x) for x in out)
 
 
 def last_error() -> str:

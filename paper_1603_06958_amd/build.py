@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfamsa_lcs.so")
-SOURCES = ["lcs_kernels.hip", "mst.hip", "gapped.hip", "peak.hip", "noalloc.hip", "runtime.cpp", "plan.cpp", "autotune.cpp", "slink.cpp", "server.cpp", "guide_tree.cpp"]
+SOURCES = ["lcs_kernels.hip", "mst.hip", "gapped.hip", "peak.hip", "noalloc.hip", "profile_dp.hip", "runtime.cpp", "plan.cpp", "autotune.cpp", "slink.cpp", "server.cpp", "guide_tree.cpp"]
 ARCH = os.environ.get("FAMSA_LCS_ARCH", "gfx950")
 
 

@@ -1,0 +1,505 @@
+// Aligning one sequence to a profile on gfx950: the specialised dynamic
+// programming the progressive stage runs when one side of a merge is a
+// single sequence (Methods, "Progressive construction of the alignment"),
+// with the affine terminal / non-terminal gap costs and the gap-type
+// corrections of "Gap types and costs determination".
+//
+// A batch holds independent problems (the alignments of one level of the
+// guide tree).  Per problem, from the profile's K gapped rows of width n:
+//   pdp_rows_kernel -- a wave per row: the columns of its first and last
+//                      residue (ballots over 64 columns at a time);
+//   pdp_cols_kernel -- a thread per column j: the profile's per-column
+//                      symbol counters (LDS histogram over the rows), the
+//                      column-to-symbol cost table cost[a][j] = sum_x
+//                      count[j][x] S[x][a], w_j = residues in column j and
+//                      the four gap costs of a gap in the sequence against
+//                      column j (w_j times To, Te, Go, Ge); a thread per
+//                      boundary p: the cost of the first and of each further
+//                      gap column inserted into the profile there, from the
+//                      counts of rows in each of the four situations
+//                      (terminal or inside, next to a gap or opening one);
+//   pdp_dp_kernel   -- a wave per problem: the three-state DP
+//                        M(i,j) = best(i-1,j-1) + cost[a_i][j]
+//                        D(i,j) = max(M - o w_j, I - o w_j, D - e w_j)(i,j-1)
+//                        I(i,j) = max(M - f_j, D - f_j, I - x_j)(i-1,j)
+//                      over strips of 64 rows (a lane per row), each strip
+//                      swept along anti-diagonals: at step t lane l does
+//                      column t - l, takes the cell above from lane l - 1
+//                      (and lane 0 from the strip above's last row, kept in
+//                      global memory), and records the three choices of each
+//                      cell in one byte; then the wave traces one optimal
+//                      alignment back from (m, n), staging 64 steps of
+//                      choices in LDS at a time.
+// Ties take the first maximum in the order written (M, D, I), as a fixed
+// rule, so the alignment and not only its score is unique.  All DP
+// arithmetic is int64.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "runtime.h"
+
+namespace famsa {
+namespace {
+
+constexpr uint8_t kGap = FAMSA_PROFILE_GAP;
+constexpr int64_t kNeg = INT64_MIN / 4;
+double g_profile_dp_ms = 0;  // duration of the last batch's DP launch
+
+struct PdpProb {        // one problem's offsets into the batch arrays
+  uint64_t seq;         // seqs (bytes)
+  uint64_t rows;        // rows (bytes), K rows of n
+  uint64_t cost;        // cost (int32), sigma x n
+  uint64_t col;         // w (int32, n); dgap (int64, 4 n); ifirst, iext (int64, n + 1)
+  uint64_t rowx;        // first, last (int32, K)
+  uint64_t edge;        // edge (int64, 3 (n + 1))
+  uint64_t dir;         // dir (bytes): row 0, then strips of (n + 64) x 64
+  uint64_t ops;         // ops (bytes), m + n
+  uint32_t m, n, K, pad;
+};
+
+struct PdpArrays {
+  const uint8_t* seqs;
+  const uint8_t* rows;
+  int32_t* cost;
+  int32_t* w;
+  int64_t* dgap;    // [4][n] per problem: w_j To, w_j Te, w_j Go, w_j Ge
+  int64_t* ifirst;
+  int64_t* iext;
+  int32_t* first;
+  int32_t* last;
+  int64_t* edge;
+  uint8_t* dir;
+  uint8_t* ops;
+  int64_t* score;
+  uint32_t* nops;
+};
+
+__device__ __forceinline__ int argmax3(int64_t x0, int64_t x1, int64_t x2, int64_t* best) {
+  int k = 0;
+  int64_t b = x0;
+  if (x1 > b) { b = x1; k = 1; }
+  if (x2 > b) { b = x2; k = 2; }
+  *best = b;
+  return k;
+}
+
+// A wave per row: first and last column holding a residue (n and -1 if none).
+__global__ __launch_bounds__(256) void pdp_rows_kernel(const PdpProb* __restrict__ probs, PdpArrays A) {
+  const PdpProb P = probs[blockIdx.x];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (uint32_t s = wave; s < P.K; s += nw) {
+    const uint8_t* row = A.rows + P.rows + (uint64_t)s * P.n;
+    int32_t f = (int32_t)P.n, l = -1;
+    for (uint32_t c0 = 0; c0 < P.n; c0 += 64) {
+      const uint32_t c = c0 + lane;
+      const bool res = c < P.n && row[c] != kGap;
+      const uint64_t b = __ballot(res);
+      if (b) {
+        if (f == (int32_t)P.n) f = (int32_t)(c0 + __builtin_ctzll(b));
+        l = (int32_t)(c0 + 63 - __builtin_clzll(b));
+      }
+    }
+    if (lane == 0) {
+      A.first[P.rowx + s] = f;
+      A.last[P.rowx + s] = l;
+    }
+  }
+}
+
+// blockIdx.y picks 256 columns (boundaries) of problem blockIdx.x.
+__global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict__ probs, PdpArrays A,
+                                                       const int32_t* __restrict__ subst, uint32_t sigma, int64_t To,
+                                                       int64_t Te, int64_t Go, int64_t Ge) {
+  __shared__ uint32_t hist[FAMSA_LCS_MAX_ALPHABET][256];
+  __shared__ int32_t S[FAMSA_LCS_MAX_ALPHABET * FAMSA_LCS_MAX_ALPHABET];
+  const PdpProb P = probs[blockIdx.x];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t j = blockIdx.y * 256u + tid;  // column j (0-based) and boundary p = j
+  if (blockIdx.y * 256u > P.n) return;          // whole block past the last boundary
+  for (uint32_t e = tid; e < sigma * sigma; e += 256) S[e] = subst[e];
+  for (uint32_t x = 0; x < sigma; ++x) hist[x][tid] = 0;
+  __syncthreads();
+  if (j > P.n) return;
+  const uint8_t* rows = A.rows + P.rows;
+  uint32_t cTA = 0, cTO = 0, cIA = 0, cIO = 0;  // boundary situations: terminal/inside x next to a gap/opening
+  for (uint32_t s = 0; s < P.K; ++s) {
+    const uint8_t* row = rows + (uint64_t)s * P.n;
+    const uint32_t x = j < P.n ? row[j] : kGap;
+    if (x != kGap) ++hist[x][tid];
+    const bool gap_right = j < P.n && x == kGap;
+    const bool gap_left = j >= 1 && row[j - 1] == kGap;
+    const int32_t f = A.first[P.rowx + s], l = A.last[P.rowx + s];
+    const bool inside = f < (int32_t)j && l >= (int32_t)j;  // residues on both sides of the boundary
+    const bool adj = gap_left || gap_right;
+    if (inside) { if (adj) ++cIA; else ++cIO; }
+    else { if (adj) ++cTA; else ++cTO; }
+  }
+  A.ifirst[P.col + j] = (int64_t)cTA * Te + (int64_t)cTO * To + (int64_t)cIA * Ge + (int64_t)cIO * Go;
+  A.iext[P.col + j] = (int64_t)(cTA + cTO) * Te + (int64_t)(cIA + cIO) * Ge;
+  if (j == P.n) return;
+  int32_t wj = 0;
+  for (uint32_t x = 0; x < sigma; ++x) wj += (int32_t)hist[x][tid];
+  A.w[P.col + j] = wj;
+  int64_t* dg = A.dgap + 4 * P.col;
+  dg[j] = (int64_t)wj * To;
+  dg[P.n + j] = (int64_t)wj * Te;
+  dg[2 * P.n + j] = (int64_t)wj * Go;
+  dg[3 * P.n + j] = (int64_t)wj * Ge;
+  for (uint32_t a = 0; a < sigma; ++a) {
+    int32_t c = 0;
+    for (uint32_t x = 0; x < sigma; ++x) c += (int32_t)hist[x][tid] * S[x * sigma + a];
+    A.cost[P.cost + (uint64_t)a * P.n + j] = c;
+  }
+}
+
+__device__ __forceinline__ int64_t shfl_up64(int64_t v) {
+  const int32_t lo = __shfl_up((int32_t)(uint32_t)(uint64_t)v, 1, 64);
+  const int32_t hi = __shfl_up((int32_t)(uint32_t)((uint64_t)v >> 32), 1, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Region of a problem's choice bytes: row 0 (rounded up to 64 bytes), then
+// per strip of 64 rows (n + 64) steps x 64 lanes.  Cell (i, j), i >= 1, is
+// byte t * 64 + l of strip (i - 1) / 64, with l = (i - 1) mod 64, t = j + l.
+__host__ __device__ inline uint64_t pdp_row0_bytes(uint32_t n) { return ((uint64_t)n + 1 + 63) & ~(uint64_t)63; }
+__host__ __device__ inline uint64_t pdp_strip_bytes(uint32_t n) { return ((uint64_t)n + 64) * 64; }
+__host__ __device__ inline uint64_t pdp_dir_bytes(uint32_t m, uint32_t n) {
+  return pdp_row0_bytes(n) + (uint64_t)((m + 63) / 64) * pdp_strip_bytes(n);
+}
+
+__device__ __forceinline__ int64_t bcast64(int64_t v, uint32_t src) {
+  const int32_t lo = __shfl((int32_t)(uint32_t)(uint64_t)v, (int)src, 64);
+  const int32_t hi = __shfl((int32_t)(uint32_t)((uint64_t)v >> 32), (int)src, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ probs, PdpArrays A) {
+  __shared__ uint4 stage4[256];  // 4 KB window of choice bytes
+  const uint8_t* stage = reinterpret_cast<const uint8_t*>(stage4);
+  const PdpProb P = probs[blockIdx.x];
+  const uint32_t lane = threadIdx.x, m = P.m, n = P.n;
+  const int64_t* dto = A.dgap + 4 * P.col;
+  const int64_t* dte = dto + n;
+  const int64_t* dgo = dto + 2 * n;
+  const int64_t* dge = dto + 3 * n;
+  const int64_t* ifirst = A.ifirst + P.col;
+  const int64_t* iext = A.iext + P.col;
+  int64_t* edge = A.edge + P.edge;  // [j][M, D, I] of the row above the current strip
+  uint8_t* dir = A.dir + P.dir;
+  uint8_t* strips = dir + pdp_row0_bytes(n);
+  // row 0: gaps in the sequence before its first residue (terminal costs)
+  if (lane == 0) {
+    int64_t Mp = 0, Dp = kNeg, Ip = kNeg;
+    for (uint32_t j = 0; j <= n; ++j) {
+      int64_t M = kNeg, D = kNeg, b;
+      const int64_t I = kNeg;
+      int ds = 0;
+      if (j == 0) M = 0;
+      else ds = argmax3(Mp - dto[j - 1], Ip - dto[j - 1], Dp - dte[j - 1], &D);
+      const int bk = argmax3(M, D, I, &b);
+      dir[j] = (uint8_t)(bk | (ds << 2));
+      edge[3 * j] = M;
+      edge[3 * j + 1] = D;
+      edge[3 * j + 2] = I;
+      Mp = M;
+      Dp = D;
+      Ip = I;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  int64_t Mc = kNeg, Dc = kNeg, Ic = kNeg;
+  for (uint32_t i0 = 0; i0 < m; i0 += 64) {
+    const uint32_t i = i0 + 1 + lane;
+    const bool active = i <= m;
+    const bool terminal = i == m;  // gaps after the sequence's last residue
+    const int64_t* po = terminal ? dto : dgo;
+    const int64_t* pe = terminal ? dte : dge;
+    const uint32_t a = active ? A.seqs[P.seq + i - 1] : 0u;
+    const int32_t* crow = A.cost + P.cost + (uint64_t)a * n;
+    const bool writes_edge = lane == 63 && i0 + 64 < m;
+    uint8_t* dstrip = strips + (uint64_t)(i0 >> 6) * pdp_strip_bytes(n) + lane;
+    int64_t diag = kNeg;
+    Mc = Dc = Ic = kNeg;
+    for (uint32_t t = 0; t < n + 64; ++t) {
+      int64_t Mu = shfl_up64(Mc), Du = shfl_up64(Dc), Iu = shfl_up64(Ic);
+      const int32_t j = (int32_t)t - (int32_t)lane;
+      if (lane == 0 && j <= (int32_t)n) {
+        Mu = edge[3 * j];
+        Du = edge[3 * j + 1];
+        Iu = edge[3 * j + 2];
+      }
+      if (active && j >= 0 && j <= (int32_t)n) {
+        int64_t M = kNeg, D = kNeg, I, b;
+        int ds = 0;
+        if (j >= 1) {
+          M = diag + (int64_t)crow[j - 1];
+          ds = argmax3(Mc - po[j - 1], Ic - po[j - 1], Dc - pe[j - 1], &D);
+        }
+        const int is = argmax3(Mu - ifirst[j], Du - ifirst[j], Iu - iext[j], &I);
+        const int bk = argmax3(M, D, I, &b);
+        dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
+        argmax3(Mu, Du, Iu, &diag);  // the cell above is the next column's diagonal
+        Mc = M;
+        Dc = D;
+        Ic = I;
+        if (writes_edge) {
+          edge[3 * j] = M;
+          edge[3 * j + 1] = D;
+          edge[3 * j + 2] = I;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // the cell (m, n): held by the lane of row m, or row 0 when m = 0
+  int64_t fM, fD, fI;
+  if (m) {
+    const uint32_t src = (m - 1) & 63u;
+    fM = bcast64(Mc, src);
+    fD = bcast64(Dc, src);
+    fI = bcast64(Ic, src);
+  } else {
+    fM = edge[3 * n];
+    fD = edge[3 * n + 1];
+    fI = edge[3 * n + 2];
+  }
+  int64_t best;
+  int st = argmax3(fM, fD, fI, &best);
+  // trace back; every lane walks the same path (uniform control flow), the
+  // choice bytes come through a 4 KB LDS window
+  uint8_t* ops = A.ops + P.ops;
+  uint32_t i = m, j = n, k = 0;
+  int win = -2;        // window's region: -1 row 0, s >= 0 strip s
+  uint64_t wlo = 0;    // window's first byte in its region
+  while (i > 0 || j > 0) {
+    // the byte this step needs: the current cell for D and I, the diagonal
+    // cell for M (after the move)
+    uint32_t ci = i, cj = j;
+    if (st == 0) {
+      if (i == 0 || j == 0) break;  // cannot happen for a consistent matrix
+      ci = i - 1;
+      cj = j - 1;
+    } else if (st == 1) {
+      if (j == 0) break;
+    } else if (i == 0) {
+      break;
+    }
+    if (lane == 0) ops[k] = (uint8_t)st;
+    ++k;
+    const int region = ci == 0 ? -1 : (int)((ci - 1) >> 6);
+    const uint64_t idx = ci == 0 ? cj : (uint64_t)(cj + ((ci - 1) & 63u)) * 64 + ((ci - 1) & 63u);
+    if (region != win || idx < wlo || idx >= wlo + 4096) {
+      const uint8_t* base = region < 0 ? dir : strips + (uint64_t)region * pdp_strip_bytes(n);
+      const uint64_t size = region < 0 ? pdp_row0_bytes(n) : pdp_strip_bytes(n);
+      win = region;
+      wlo = idx >= 4032 ? ((idx - 4032) & ~(uint64_t)63) : 0;
+      __syncthreads();  // the previous window's reads are done
+      const uint64_t off = wlo + (uint64_t)lane * 64;
+      if (off < size) {
+        const uint4* src = reinterpret_cast<const uint4*>(base + off);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) stage4[lane * 4 + q] = src[q];
+      }
+      __syncthreads();
+    }
+    const uint32_t byte = stage[idx - wlo];
+    if (st == 0) {
+      i = ci;
+      j = cj;
+      st = (int)(byte & 3u);
+    } else if (st == 1) {
+      const uint32_t s = (byte >> 2) & 3u;
+      --j;
+      st = s == 0 ? 0 : (s == 1 ? 2 : 1);
+    } else {
+      const uint32_t s = (byte >> 4) & 3u;
+      --i;
+      st = s == 0 ? 0 : (s == 1 ? 1 : 2);
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (uint32_t x = lane; x < k / 2; x += 64) {  // ops were written from the last column back
+    const uint8_t u = ops[x], v = ops[k - 1 - x];
+    ops[x] = v;
+    ops[k - 1 - x] = u;
+  }
+  if (lane == 0) {
+    A.score[blockIdx.x] = best;
+    A.nops[blockIdx.x] = (i == 0 && j == 0) ? k : 0xFFFFFFFFu;  // all ones: the walk stopped early
+  }
+}
+
+}  // namespace
+
+static uint64_t up256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+}  // namespace famsa
+
+extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const uint64_t* seq_off, const uint8_t* rows,
+                                   const uint64_t* rows_off, const uint32_t* nrows, const uint32_t* width,
+                                   uint32_t alphabet_size, const int32_t* subst, const int64_t* gap_costs, int device,
+                                   int64_t* score, uint8_t* ops, const uint64_t* ops_off, uint32_t* nops) {
+  using namespace famsa;
+  if (nprob == 0) return 0;
+  if (nprob > FAMSA_PROFILE_MAX_PROBLEMS)
+    return set_error(FAMSA_LCS_EINVAL, "%u problems (at most %u)", nprob, FAMSA_PROFILE_MAX_PROBLEMS);
+  if (!seq_off || !rows_off || !nrows || !width || !subst || !gap_costs || !score || !ops || !ops_off || !nops)
+    return set_error(FAMSA_LCS_EINVAL, "NULL argument");
+  if (alphabet_size < 1 || alphabet_size > FAMSA_LCS_MAX_ALPHABET)
+    return set_error(FAMSA_LCS_EINVAL, "alphabet_size %u not in [1, %u]", alphabet_size, FAMSA_LCS_MAX_ALPHABET);
+  const uint32_t sigma = alphabet_size;
+  for (uint32_t e = 0; e < sigma * sigma; ++e)
+    if (subst[e] > (int32_t)FAMSA_PROFILE_MAX_SUBST || subst[e] < -(int32_t)FAMSA_PROFILE_MAX_SUBST)
+      return set_error(FAMSA_LCS_EINVAL, "substitution score %d outside [-%u, %u]", subst[e],
+                       FAMSA_PROFILE_MAX_SUBST, FAMSA_PROFILE_MAX_SUBST);
+  for (int c = 0; c < 4; ++c)
+    if (gap_costs[c] > (int64_t)FAMSA_PROFILE_MAX_GAP || gap_costs[c] < -(int64_t)FAMSA_PROFILE_MAX_GAP)
+      return set_error(FAMSA_LCS_EINVAL, "gap cost %lld outside [-%u, %u]", (long long)gap_costs[c],
+                       FAMSA_PROFILE_MAX_GAP, FAMSA_PROFILE_MAX_GAP);
+  std::vector<PdpProb> pr(nprob);
+  uint64_t o_seq = 0, o_rows = 0, o_cost = 0, o_col = 0, o_rowx = 0, o_edge = 0, o_dir = 0, o_ops = 0;
+  uint32_t nmax = 0;
+  for (uint32_t p = 0; p < nprob; ++p) {
+    if (seq_off[p + 1] < seq_off[p]) return set_error(FAMSA_LCS_EINVAL, "seq_off decreases at %u", p);
+    const uint64_t m = seq_off[p + 1] - seq_off[p];
+    const uint32_t K = nrows[p], n = width[p];
+    if (m > FAMSA_LCS_MAX_LEN) return set_error(FAMSA_LCS_EINVAL, "problem %u: sequence length %llu", p,
+                                                (unsigned long long)m);
+    if (K < 1 || K > FAMSA_PROFILE_MAX_ROWS)
+      return set_error(FAMSA_LCS_EINVAL, "problem %u: %u profile rows (1..%u)", p, K, FAMSA_PROFILE_MAX_ROWS);
+    if (n > FAMSA_LCS_MAX_LEN) return set_error(FAMSA_LCS_EINVAL, "problem %u: profile width %u", p, n);
+    if (m && !seqs) return set_error(FAMSA_LCS_EINVAL, "seqs is NULL");
+    if (n && !rows) return set_error(FAMSA_LCS_EINVAL, "rows is NULL");
+    for (uint64_t x = seq_off[p]; x < seq_off[p + 1]; ++x)
+      if (seqs[x] >= sigma)
+        return set_error(FAMSA_LCS_EINVAL, "problem %u: sequence code %u not below alphabet_size %u", p, seqs[x],
+                         sigma);
+    const uint8_t* r = rows ? rows + rows_off[p] : nullptr;
+    for (uint64_t x = 0; x < (uint64_t)K * n; ++x)
+      if (r[x] != FAMSA_PROFILE_GAP && r[x] >= sigma)
+        return set_error(FAMSA_LCS_EINVAL, "problem %u: profile code %u is neither a gap nor below %u", p, r[x],
+                         sigma);
+    PdpProb& d = pr[p];
+    d.m = (uint32_t)m;
+    d.n = n;
+    d.K = K;
+    d.pad = 0;
+    d.seq = o_seq;
+    d.rows = o_rows;
+    d.cost = o_cost;
+    d.col = o_col;
+    d.rowx = o_rowx;
+    d.edge = o_edge;
+    d.dir = o_dir;
+    d.ops = o_ops;
+    o_seq += m;
+    o_rows += (uint64_t)K * n;
+    o_cost += (uint64_t)sigma * n;
+    o_col += (uint64_t)n + 1;
+    o_rowx += K;
+    o_edge += 3 * ((uint64_t)n + 1);
+    o_dir += pdp_dir_bytes((uint32_t)m, n);
+    o_ops += m + n;
+    nmax = std::max(nmax, n);
+  }
+  // one device allocation, 256-byte aligned parts
+  uint64_t off = 0;
+  auto part = [&](uint64_t bytes) {
+    const uint64_t at = off;
+    off += up256(bytes ? bytes : 1);
+    return at;
+  };
+  const uint64_t b_probs = part(sizeof(PdpProb) * nprob), b_subst = part(4ull * sigma * sigma),
+                 b_seqs = part(o_seq), b_rows = part(o_rows), b_cost = part(4 * o_cost), b_w = part(4 * o_col),
+                 b_dgap = part(32 * o_col), b_if = part(8 * o_col), b_ie = part(8 * o_col), b_first = part(4 * o_rowx),
+                 b_last = part(4 * o_rowx), b_edge = part(8 * o_edge), b_dir = part(o_dir), b_ops = part(o_ops),
+                 b_score = part(8ull * nprob), b_nops = part(4ull * nprob);
+  FAMSA_HIP(hipSetDevice(device));
+  hipStream_t st = nullptr;
+  int rc = lib_stream(device, 0, &st);
+  if (rc) return rc;
+  DevMem mem;
+  rc = mem.alloc(off);
+  if (rc) return rc;
+  uint8_t* D = mem.as<uint8_t>();
+  std::vector<uint8_t> hseq(o_seq ? o_seq : 1), hrows(o_rows ? o_rows : 1);
+  for (uint32_t p = 0; p < nprob; ++p) {
+    if (pr[p].m) memcpy(hseq.data() + pr[p].seq, seqs + seq_off[p], pr[p].m);
+    const uint64_t rb = (uint64_t)pr[p].K * pr[p].n;
+    if (rb) memcpy(hrows.data() + pr[p].rows, rows + rows_off[p], rb);
+  }
+  FAMSA_HIP(hipMemcpyAsync(D + b_probs, pr.data(), sizeof(PdpProb) * nprob, hipMemcpyHostToDevice, st));
+  FAMSA_HIP(hipMemcpyAsync(D + b_subst, subst, 4ull * sigma * sigma, hipMemcpyHostToDevice, st));
+  if (o_seq) FAMSA_HIP(hipMemcpyAsync(D + b_seqs, hseq.data(), o_seq, hipMemcpyHostToDevice, st));
+  if (o_rows) FAMSA_HIP(hipMemcpyAsync(D + b_rows, hrows.data(), o_rows, hipMemcpyHostToDevice, st));
+  PdpArrays A;
+  A.seqs = D + b_seqs;
+  A.rows = D + b_rows;
+  A.cost = reinterpret_cast<int32_t*>(D + b_cost);
+  A.w = reinterpret_cast<int32_t*>(D + b_w);
+  A.dgap = reinterpret_cast<int64_t*>(D + b_dgap);
+  A.ifirst = reinterpret_cast<int64_t*>(D + b_if);
+  A.iext = reinterpret_cast<int64_t*>(D + b_ie);
+  A.first = reinterpret_cast<int32_t*>(D + b_first);
+  A.last = reinterpret_cast<int32_t*>(D + b_last);
+  A.edge = reinterpret_cast<int64_t*>(D + b_edge);
+  A.dir = D + b_dir;
+  A.ops = D + b_ops;
+  A.score = reinterpret_cast<int64_t*>(D + b_score);
+  A.nops = reinterpret_cast<uint32_t*>(D + b_nops);
+  const PdpProb* dprobs = reinterpret_cast<const PdpProb*>(D + b_probs);
+  hipEvent_t ev[2];
+  FAMSA_HIP(hipEventCreate(&ev[0]));
+  FAMSA_HIP(hipEventCreate(&ev[1]));
+  hipLaunchKernelGGL(pdp_rows_kernel, dim3(nprob), dim3(256), 0, st, dprobs, A);
+  FAMSA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pdp_cols_kernel, dim3(nprob, nmax / 256 + 1), dim3(256), 0, st, dprobs, A,
+                     reinterpret_cast<const int32_t*>(D + b_subst), sigma, gap_costs[0], gap_costs[1], gap_costs[2],
+                     gap_costs[3]);
+  FAMSA_HIP(hipGetLastError());
+  FAMSA_HIP(hipEventRecord(ev[0], st));
+  hipLaunchKernelGGL(pdp_dp_kernel, dim3(nprob), dim3(64), 0, st, dprobs, A);
+  FAMSA_HIP(hipGetLastError());
+  FAMSA_HIP(hipEventRecord(ev[1], st));
+  std::vector<uint8_t> hops(o_ops ? o_ops : 1);
+  FAMSA_HIP(hipMemcpyAsync(score, D + b_score, 8ull * nprob, hipMemcpyDeviceToHost, st));
+  FAMSA_HIP(hipMemcpyAsync(nops, D + b_nops, 4ull * nprob, hipMemcpyDeviceToHost, st));
+  if (o_ops) FAMSA_HIP(hipMemcpyAsync(hops.data(), D + b_ops, o_ops, hipMemcpyDeviceToHost, st));
+  FAMSA_HIP(hipStreamSynchronize(st));
+  float ms = 0;
+  FAMSA_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  g_profile_dp_ms = ms;
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  for (uint32_t p = 0; p < nprob; ++p) {
+    if (nops[p] == 0xFFFFFFFFu) return set_error(FAMSA_LCS_EDEVICE, "problem %u: trace-back stopped early", p);
+    memcpy(ops + ops_off[p], hops.data() + pr[p].ops, nops[p]);
+  }
+  return 0;
+}
+
+extern "C" double famsa_profile_last_dp_ms(void) { return famsa::g_profile_dp_ms; }
+
+extern "C" int famsa_gap_costs_scaled(uint32_t k, const double* base, double gl, double gd, int64_t* out) {
+  using namespace famsa;
+  if (!base || !out) return set_error(FAMSA_LCS_EINVAL, "NULL argument");
+  if (k == 0 || !(gl > 0) || gd == 0) return set_error(FAMSA_LCS_EINVAL, "k = %u, gl = %g, gd = %g", k, gl, gd);
+  const double g = 1.0 + log((double)k / gl) / gd;
+  for (int c = 0; c < 4; ++c) {
+    const double x = base[c] * g;
+    const double r = floor(fabs(x) + 0.5);
+    if (!(r <= (double)FAMSA_PROFILE_MAX_GAP))
+      return set_error(FAMSA_LCS_EINVAL, "scaled gap cost %g beyond %u", x, FAMSA_PROFILE_MAX_GAP);
+    out[c] = (int64_t)r * (x >= 0 ? 1 : -1);
+  }
+  return 0;
+}

@@ -258,3 +258,79 @@ def stats(b: Batch) -> dict:
 
 
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
+
+
+# ---------------------------------------------------------------- profiles
+
+GAP = 0xFF  # a gap in a gapped profile row
+
+
+@dataclasses.dataclass
+class ProfileProblem:
+    """One sequence to align to a profile of K gapped rows of width n."""
+    seq: np.ndarray    # uint8, m codes
+    rows: np.ndarray   # uint8, K x n, codes or GAP
+
+
+def synthetic_subst(sigma: int, seed: int) -> np.ndarray:
+    """A symmetric integer substitution matrix (sigma x sigma, int32): the
+    diagonal uniform in [4, 12], the rest uniform in [-4, 2].  The paper
+    names MIQS but does not print its values, so a synthetic matrix of that
+    shape stands in for it."""
+    rng = np.random.default_rng(seed)
+    S = rng.integers(-4, 3, (sigma, sigma))
+    S = np.triu(S) + np.triu(S, 1).T
+    S[np.arange(sigma), np.arange(sigma)] = rng.integers(4, 13, sigma)
+    return S.astype(np.int32)
+
+
+def profile_problem(m_target: int, n: int, K: int, rng: np.random.Generator, alphabet: int = ALPHABET,
+                    p_conserved: float = 0.7, p_open: float = 0.05, p_terminal: float = 0.3,
+                    p_empty_row: float = 0.0) -> ProfileProblem:
+    """A profile whose columns are noisy copies of a random consensus, and a
+    sequence drawn near the same consensus.
+
+    Each row: with probability ``p_terminal`` a leading and (independently) a
+    trailing gap run of uniform length up to n/4; inside, gap runs open with
+    probability ``p_open`` per column and have Geometric(1/3) lengths; every
+    other column holds the consensus symbol with probability ``p_conserved``,
+    else a uniform one.  With probability ``p_empty_row`` a row is all gaps.
+    The sequence: the consensus resampled to ``m_target`` positions (drop or
+    repeat evenly), 10% of residues substituted.
+    """
+    cons = rng.integers(0, alphabet, max(n, 1)).astype(np.uint8)
+    rows = np.full((K, n), GAP, dtype=np.uint8)
+    for s in range(K):
+        if n == 0 or rng.random() < p_empty_row:
+            continue
+        lead = int(rng.integers(0, n // 4 + 1)) if rng.random() < p_terminal else 0
+        trail = int(rng.integers(0, n // 4 + 1)) if rng.random() < p_terminal else 0
+        c = lead
+        while c < n - trail:
+            if rng.random() < p_open:
+                c += int(rng.geometric(1.0 / 3.0))
+                continue
+            rows[s, c] = cons[c] if rng.random() < p_conserved else rng.integers(0, alphabet)
+            c += 1
+    if m_target <= 0:
+        seq = np.zeros(0, np.uint8)
+    else:
+        idx = np.minimum((np.arange(m_target) * max(n, 1)) // m_target, max(n, 1) - 1)
+        seq = cons[idx].copy()
+        hit = rng.random(m_target) < 0.1
+        seq[hit] = rng.integers(0, alphabet, int(hit.sum()))
+    return ProfileProblem(seq.astype(np.uint8), rows)
+
+
+def profile_batch(nprob: int, seed: int, m_range=(50, 400), K_range=(1, 200), alphabet: int = ALPHABET):
+    """A progressive-stage level: ``nprob`` independent problems, profile
+    width log-uniform in ``m_range``, the sequence within +-15% of it, and
+    K log-uniform in ``K_range``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nprob):
+        n = _log_uniform_int(rng, *m_range)
+        m = max(1, int(round(n * rng.uniform(0.85, 1.15))))
+        K = _log_uniform_int(rng, *K_range)
+        out.append(profile_problem(m, n, K, rng, alphabet))
+    return out

@@ -158,3 +158,40 @@ def test_noalloc_rejects_on_the_host():
     assert L.famsa_lcs_family_noalloc(1, 1, 10, 20, None, None, 0, None) == B.EINVAL
     assert L.famsa_lcs_family_noalloc(1, 1, 10, 20, 1, None, -1, None) == B.EINVAL
 
+
+def test_gap_costs_scaled_matches_the_oracle():
+    # the library's host helper against the oracle's reading of g_scale
+    from oracle import profile as OP
+    for k in (1, 2, 44, 45, 46, 300, 100_000, 415_519):
+        for base in ((10, 2, 14, 3), (7.5, 0.5, -3.5, 2.25), (0, 0, 0, 0)):
+            assert B.gap_costs_scaled(k, base) == OP.scaled_gap_costs(k, base)
+    with pytest.raises(B.FamsaError):
+        B.gap_costs_scaled(0, (1, 1, 1, 1))
+
+
+def test_profile_align_rejects_on_the_host():
+    from paper_1603_06958_amd import inputs
+    S = inputs.synthetic_subst(20, 1)
+    p = inputs.profile_problem(10, 12, 2, np.random.default_rng(0))
+    bad = p.rows.copy()
+    bad[1, 3] = 21  # neither a gap nor a code below the alphabet size
+    for probs, kw in [([(p.seq, bad)], {}), ([(p.seq, np.zeros((0, 12), np.uint8))], {}),
+                      ([(np.array([20], np.uint8), p.rows)], {}), ([(p.seq, p.rows)], {"alphabet_size": 33})]:
+        with pytest.raises(B.FamsaError) as e:
+            B.profile_align(probs, S, (1, 1, 1, 1), **kw)
+        assert e.value.code == B.EINVAL
+    with pytest.raises(B.FamsaError) as e:
+        B.profile_align([(p.seq, p.rows)], S, (1, 1, 1, 2 ** 21))
+    assert e.value.code == B.EINVAL
+
+
+def test_profile_align_accepts_valid_input_up_to_the_device():
+    # negative scores and costs are valid; without a GPU the call fails only
+    # at the device (EDEVICE), never in validation
+    from paper_1603_06958_amd import inputs
+    S = inputs.synthetic_subst(20, 1)
+    p = inputs.profile_problem(10, 12, 2, np.random.default_rng(0))
+    try:
+        B.profile_align([(p.seq, p.rows)], S, (-3, 0, 2, -1))
+    except B.FamsaError as e:
+        assert e.code == B.EDEVICE, e

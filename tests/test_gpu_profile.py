@@ -1,0 +1,88 @@
+"""Aligning one sequence to a profile on the GPU (famsa_profile_align)
+against the oracle (oracle/profile.py: column costs, gap-type rules and the
+affine-gap DP derived from the gapped rows): the same optimal score and the
+same alignment, op for op, under the fixed tie rule; and the GPU alignment's
+score recomputed from the rows equals the GPU score."""
+import numpy as np
+import pytest
+
+from oracle import profile as OP
+from paper_1603_06958_amd import binding as B
+from paper_1603_06958_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def check_batch(problems, S, costs, sigma=None):
+    print(f"profile batch: {len(problems)} problems, sigma {S.shape[0]}", flush=True)
+    got_s, got_ops = B.profile_align([(p.seq, p.rows) for p in problems], S, costs, alphabet_size=sigma)
+    for q, p in enumerate(problems):
+        exp_s, exp_ops = OP.align(p.seq, p.rows, S, costs)
+        assert int(got_s[q]) == exp_s, f"problem {q} (m={p.seq.size}, K,n={p.rows.shape}): score {got_s[q]} != {exp_s}"
+        assert got_ops[q].tolist() == exp_ops, f"problem {q}: alignment differs from the oracle's"
+        assert OP.alignment_score(p.seq, p.rows, S, costs, got_ops[q].tolist()) == exp_s
+
+
+def test_shapes_and_edges():
+    # strips of 64 rows (m = 63, 64, 65, 128, 129), empty sequence or profile,
+    # single rows and columns, all-gap rows and columns
+    rng = np.random.default_rng(11)
+    S = inputs.synthetic_subst(20, 1)
+    costs = OP.scaled_gap_costs(300, (9, 2, 12, 3))
+    probs = []
+    for m, n, K in [(0, 0, 1), (0, 7, 3), (5, 0, 2), (1, 1, 1), (63, 70, 4), (64, 64, 3), (65, 40, 5),
+                    (128, 130, 2), (129, 100, 6), (40, 129, 8), (200, 3, 2), (3, 200, 3), (150, 150, 12)]:
+        probs.append(inputs.profile_problem(m, n, K, rng))
+    empty = inputs.profile_problem(30, 40, 5, rng)
+    empty.rows[2, :] = inputs.GAP          # a row of gaps only
+    empty.rows[:, 7] = inputs.GAP          # a column of gaps only
+    probs.append(empty)
+    probs.append(inputs.profile_problem(60, 50, 6, rng, p_empty_row=0.5, p_terminal=0.9))
+    check_batch(probs, S, costs)
+
+
+@pytest.mark.parametrize("seed,sigma", [(21, 20), (22, 32), (23, 2)])
+def test_random_levels(seed, sigma):
+    rng = np.random.default_rng(seed)
+    S = inputs.synthetic_subst(sigma, seed)
+    costs = OP.scaled_gap_costs(int(rng.integers(50, 5000)), (8, 1, 11, 2))
+    probs = [inputs.profile_problem(int(rng.integers(1, 220)), int(rng.integers(1, 200)), int(rng.integers(1, 16)),
+                                    rng, alphabet=sigma) for _ in range(24)]
+    check_batch(probs, S, costs)
+
+
+def test_ties_everywhere():
+    # one-letter and two-letter alphabets with flat scores: many optimal
+    # alignments, so the result rests on the tie rule alone
+    rng = np.random.default_rng(31)
+    for sigma, S in [(1, np.zeros((1, 1), np.int32)), (2, np.ones((2, 2), np.int32))]:
+        probs = [inputs.profile_problem(int(rng.integers(1, 90)), int(rng.integers(1, 90)), int(rng.integers(1, 6)),
+                                        rng, alphabet=sigma) for _ in range(10)]
+        check_batch(probs, S, (0, 0, 0, 0))
+        check_batch(probs, S, (1, 1, 1, 1))
+
+
+def test_negative_and_zero_costs():
+    rng = np.random.default_rng(41)
+    S = inputs.synthetic_subst(20, 4)
+    probs = [inputs.profile_problem(int(rng.integers(1, 120)), int(rng.integers(1, 120)), int(rng.integers(1, 8)), rng)
+             for _ in range(8)]
+    check_batch(probs, S, (-2, 0, 3, -1))
+
+
+def test_long_problem():
+    # many strips and trace-back windows: m = 1500, n = 1300
+    rng = np.random.default_rng(51)
+    S = inputs.synthetic_subst(20, 5)
+    check_batch([inputs.profile_problem(1500, 1300, 3, rng)], S, OP.scaled_gap_costs(1000, (9, 2, 12, 3)))
+
+
+def test_rejects_bad_input():
+    S = inputs.synthetic_subst(20, 1)
+    p = inputs.profile_problem(10, 10, 2, np.random.default_rng(0))
+    bad = p.rows.copy()
+    bad[0, 0] = 25
+    with pytest.raises(B.FamsaError):
+        B.profile_align([(p.seq, bad)], S, (1, 1, 1, 1))
+    with pytest.raises(B.FamsaError):
+        B.profile_align([(p.seq, np.zeros((0, 10), np.uint8))], S, (1, 1, 1, 1))
