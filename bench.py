@@ -321,6 +321,48 @@ def run_peak(variants=(0,), blocks_per_cu=8, iters=20000):
     return out
 
 
+PROFILE_DP_OPS_PER_CELL = 40  # int32 lane-ops of one DP cell: 8 int64 add/sub (2 each), 4 three-way int64 maxima
+                              # (2 compares and 2 two-register selects each)
+
+
+def run_profile_dp(nprob=2048, seed=12, reps=3, cpu_problems=12):
+    """Aligning one sequence to a profile (famsa_profile_align) on a synthetic
+    progressive-stage level: `nprob` independent problems, profile width
+    log-uniform in [50, 500], sequence within 15% of it, 1..200 rows; DP
+    cells per second from HIP events around the DP launch, and the oracle's
+    rate on a few of the same problems."""
+    from oracle import profile as OP
+    from paper_1603_06958_amd import binding as B, inputs
+    probs = inputs.profile_batch(nprob, seed, m_range=(50, 500), K_range=(1, 200))
+    S = inputs.synthetic_subst(20, seed)
+    costs = OP.scaled_gap_costs(10000, (9, 2, 12, 3))
+    pairs = [(p.seq, p.rows) for p in probs]
+    cells = sum((p.seq.size + 1) * (p.rows.shape[1] + 1) for p in probs)
+    B.profile_align(pairs, S, costs)  # warm-up
+    walls, dps = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        B.profile_align(pairs, S, costs)
+        walls.append(time.perf_counter() - t0)
+        dps.append(B.profile_last_dp_ms())
+    dp_ms = float(np.median(dps))
+    t0 = time.perf_counter()
+    cpu_cells = 0
+    for p in probs[:cpu_problems]:
+        OP.align(p.seq, p.rows, S, costs)
+        cpu_cells += (p.seq.size + 1) * (p.rows.shape[1] + 1)
+    cpu_s = time.perf_counter() - t0
+    achieved = cells / (dp_ms / 1e3) * PROFILE_DP_OPS_PER_CELL
+    return {"workload": f"{nprob} sequence-to-profile problems, width log-uniform [50,500], rows log-uniform [1,200], "
+                        f"seed {seed}", "cells": int(cells), "dp_kernel_ms": round(dp_ms, 3),
+            "dp_gcups": round(cells / (dp_ms / 1e3) / 1e9, 2), "call_ms": round(1e3 * float(np.median(walls)), 2),
+            "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_INT_OPS / 1e12, 3),
+                         "unit": "Tops/s (int32 VALU)", "frac": round(achieved / PEAK_INT_OPS, 4),
+                         "ops_per_cell": PROFILE_DP_OPS_PER_CELL, "kernel": "pdp_dp_kernel"},
+            "cpu_baseline": {"value": round(cpu_cells / cpu_s / 1e9, 4), "unit": "GCUPS", "cores": 1, "kind": "oracle",
+                             "sample": f"the first {cpu_problems} problems through oracle.profile.align"}}
+
+
 def run_c3(passes=5):
     from paper_1603_06958_amd import binding as B, inputs
     b = inputs.c3()
@@ -372,6 +414,8 @@ def main():
                     help="only run a plain device copy of 1 GiB (for scaling HBM byte counters)")
     ap.add_argument("--peak", action="store_true",
                     help="only run the integer-VALU ceiling microbenchmark (all four instruction variants)")
+    ap.add_argument("--profile-dp", action="store_true",
+                    help="only run the sequence-to-profile alignment measurement")
     ap.add_argument("--consumer-alone", action="store_true",
                     help="only time the GPU single-linkage consumer over the workload's tiles kept in HBM")
     a = ap.parse_args()
@@ -386,6 +430,9 @@ def main():
         return
     if a.peak:
         print(json.dumps({"valu_peak": run_peak(variants=(0, 1, 2, 3))}), flush=True)
+        return
+    if a.profile_dp:
+        print(json.dumps({"profile_dp": run_profile_dp()}), flush=True)
         return
     if a.consumer_alone:
         from paper_1603_06958_amd import inputs
@@ -415,6 +462,7 @@ def main():
     per_launch_cells = kst[-1].cells[cls] / max(1, kst[-1].launches[cls])
     achieved = per_launch_cells * OPS_PER_CELL / (kms / 1e3)
     kname = f"lcs_fast_kernel<{cls},20>"
+    peak_meas = run_peak(variants=(0,))["recurrence (and, addc chain, bitop3)"]
     traffic, traffic_src = traffic_per_launch(kname)
     print(f"[bench] steps {[round(t, 3) for t in times]} s; kernel classes ms "
           f"{[round(x, 1) for x in kst[-1].kernel_ms]} launches {list(kst[-1].launches)} "
@@ -439,7 +487,12 @@ def main():
                      "traffic_unit": "HBM bytes per launch (read + write)", "traffic_source": traffic_src,
                      "kernel": kname, "avg_launch_ms": round(kms, 3),
                      "cells_per_launch": int(per_launch_cells),
-                     "ops_per_cell": "3/32 (AND, ADDC, BITOP3 per 32-cell dword)"},
+                     "ops_per_cell": "3/32 (AND, ADDC, BITOP3 per 32-cell dword)",
+                     "peak_measured": peak_meas["tops_per_s"],
+                     "frac_of_measured_peak": round(achieved / 1e12 / peak_meas["tops_per_s"], 4),
+                     "peak_measured_source": "famsa_valu_peak: register-only chains of the recurrence's three "
+                                             f"instructions on every CU at {peak_meas['clock_ghz']} GHz "
+                                             f"({peak_meas['lane_ops_per_clk_per_cu']} lane-ops/clk/CU)"},
         "launch": {"cols_per_item": int(info.cols_per_item), "waves_per_group": list(info.waves_per_group)[:3]},
     }
     if not a.no_extra:
@@ -471,6 +524,8 @@ def main():
         print(f"[bench] host_slink {res['host_slink']}", file=sys.stderr, flush=True)
         res["gapped"] = run_gapped(b)
         print(f"[bench] gapped {res['gapped']}", file=sys.stderr, flush=True)
+        res["profile_dp"] = run_profile_dp()
+        print(f"[bench] profile_dp {res['profile_dp']}", file=sys.stderr, flush=True)
     if not a.no_c3:
         res["c3"] = run_c3()
         print(f"[bench] c3 {res['c3']}", file=sys.stderr, flush=True)
