@@ -74,6 +74,10 @@ typedef enum famsa_lcs_status {
 #define FAMSA_LCS_TWO_STREAMS  0x200u /* alternate consecutive launch steps between two compute streams, so a
                                          step's tail overlaps the next step's head (on a single family of
                                          k = 100,000 this is 3% slower with graphs and equal without) */
+#define FAMSA_LCS_LONG_SEGMENTED 0x400u /* rows longer than one lane holds (896 residues; 512 for alphabets over
+                                           20) go to the segmented long-row kernel only, not to the
+                                           lanes-per-row mode (several lanes per row, carries passed across
+                                           lanes); results are the same */
 
 /* What a tile's values are (famsa_lcs_tile.values). */
 #define FAMSA_LCS_VALUES_LCS   0u
@@ -378,10 +382,14 @@ int famsa_lcs_server_memory(const famsa_lcs_server_t* srv, uint64_t* in_use, uin
 void famsa_lcs_server_destroy(famsa_lcs_server_t* srv);
 
 /* ------------------------------------------------------------------------
- * Autotuning: time candidate launch parameters (waves per group per length
- * class, columns per work item) on a sample of the plan's work and store the
- * winner in a JSON cache keyed by GPU architecture and alphabet size
- * (path: FAMSA_LCS_TUNE_CACHE, else none).  Results never change.
+ * Autotuning: time candidate launch parameters (waves per workgroup per
+ * length class, columns per work item, and for long rows the most dwords a
+ * lane holds in the lanes-per-row mode, which fixes the lanes per row and
+ * the rows per wave, or the segmented kernel) on the plan's first launch
+ * step and store the winner in a text cache, one line per GPU architecture
+ * and alphabet size ("arch/sigmaN waves0 waves1 waves2 cols long_dwords
+ * waves3"; path: cache_path, else FAMSA_LCS_TUNE_CACHE, else none).
+ * Results never change.
  * ------------------------------------------------------------------------ */
 int famsa_lcs_autotune(famsa_lcs_plan_t* plan, const char* cache_path);
 
@@ -494,7 +502,7 @@ int famsa_gap_costs_scaled(uint32_t k, const double* base, double gl, double gd,
 #define FAMSA_LCS_NOALLOC_MAX_SEQ 8192u
 #define FAMSA_LCS_NOALLOC_MAX_LEN 896u
 #define FAMSA_LCS_NOALLOC_MAX_LEN_S32 512u
-#define FAMSA_LCS_NOALLOC_SCRATCH_BYTES 33755392u
+#define FAMSA_LCS_NOALLOC_SCRATCH_BYTES 33757440u
 int famsa_lcs_family_noalloc(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
                              uint32_t alphabet_size, int32_t* out, int32_t* status, int device, void* stream);
 

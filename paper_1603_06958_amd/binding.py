@@ -21,6 +21,7 @@ PLAIN, DESCENDING, DEVICE_TILES, NO_GRAPH, NO_AUTOTUNE, ONE_STREAM = 0x1, 0x2, 0
 OUT_INDEL, OUT_SIM = 0x40, 0x80
 PLAIN_ASYNC = 0x100
 TWO_STREAMS = 0x200
+LONG_SEGMENTED = 0x400
 VALUES_LCS, VALUES_INDEL, VALUES_SIM = 0, 1, 2
 MAX_LEN = 65535
 

@@ -41,7 +41,7 @@ extern size_t g_max_lds;          // min(kMaxLds, device limit), set when a plan
 constexpr size_t kLdsReserve = 64; // static LDS of the fast kernels (queue slots) fits in this
 constexpr uint32_t kPlainBlock = 256;
 
-struct GroupDesc {          // 32 bytes
+struct GroupDesc {          // 48 bytes
   uint32_t lane_first;      // index of lane 0 in the LaneDesc array
   uint32_t nrows;           // rows in this group (1..64)
   uint32_t W;               // dwords per lane = ceil(max row length / 32), >= 1
@@ -53,8 +53,17 @@ struct GroupDesc {          // 32 bytes
                             //   rowbase[rowbase_base + c] (kNoMap with colmap_base)
   uint32_t nmap;            // mapped positions
   uint32_t shift;           // index of an unmapped position c is c + shift
+  uint32_t lpr;             // lanes per row: 0 = one lane per row (up to 64 rows, W dwords per lane); L >= 2 =
+                            //   long rows each spread over L neighbouring lanes of ceil(W / L) dwords (the
+                            //   long-row kernel's lanes-per-row mode), floor(64 / L) rows at most
+  uint32_t pad[3];
 };
 constexpr uint32_t kNoMap = 0xFFFFFFFFu;
+
+// Lanes-per-row mode: dwords per lane between kSkewWLMin and the largest a
+// lane holds in LDS (28 for alphabets up to 20, 16 up to 32).
+constexpr uint32_t kSkewWLMin = 8;
+inline uint32_t skew_wl_max(uint32_t sigma) { return sigma <= 20 ? 28u : 16u; }
 
 // A lane's row.  Columns are walked by position c; the lane needs column c
 // iff c > pos.  Its result for column index b at position c goes to
@@ -112,6 +121,14 @@ struct StepRange {          // per step: classes 0..3 index items, class 4 index
 // lane for a column of n residues.
 constexpr int kLongSegQ[2] = {7, 4};  // sigma <= 20, sigma <= 32
 inline uint32_t long_seg_q(uint32_t sigma) { return sigma <= 20 ? 7u : 4u; }
+// LDS of the long-row kernel: a segment's mask table, or the lanes-per-row
+// table (sigcap + 1 planes per quad, the last all zeros), whichever is larger.
+inline size_t long_lds_bytes(uint32_t sigma) {
+  const size_t cap = sigma <= 20 ? 20u : 32u;
+  const size_t seg = (size_t)long_seg_q(sigma) * cap * 1024u;
+  const size_t lpr = (size_t)((skew_wl_max(sigma) + 3u) / 4u) * (cap + 1u) * 1024u;
+  return seg > lpr ? seg : lpr;
+}
 
 struct DeviceBatch {
   const uint8_t* codes;

@@ -280,13 +280,13 @@ __global__ __launch_bounds__(1024) void lcs_fast_kernel(
 // carry in and, unless it is the top segment, writes its own carry out the
 // same way.  `crow` points at the lane's dword for block 0; blocks are 64
 // dwords apart (one per lane), so a wave's carry traffic is coalesced.
-template <int W, int SIG>
+template <int W, int SIG, int PL = SIG>
 __device__ __forceinline__ void long_step(uint32_t (&V)[W], const char* __restrict__ p, uint32_t& cin, uint32_t& cout) {
   constexpr int Q = (W + 3) / 4;
   uint32_t M[4 * Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const uint4 x = *reinterpret_cast<const uint4*>(p + q * (SIG * 1024));
+    const uint4 x = *reinterpret_cast<const uint4*>(p + q * (PL * 1024));
     M[4 * q + 0] = x.x;
     M[4 * q + 1] = x.y;
     M[4 * q + 2] = x.z;
@@ -359,6 +359,176 @@ __device__ __forceinline__ uint32_t long_segment_w(uint32_t w, const uint4* __re
   }
 }
 
+// ------------------------------------------------------------ lanes per row
+
+// Long rows spread over L neighbouring lanes ("lanes per row" mode): lane s
+// of a row holds dwords [s WL, (s + 1) WL) of its bit vector, so the carry of
+// every column step crosses from lane s - 1 into lane s.  The lanes run
+// skewed: at pipeline step T lane s processes the column's 32-symbol chunk
+// T - s, taking that chunk's 32 carry-in bits from lane s - 1, which
+// processed the same chunk at step T - 1, by one DPP wave shift of its
+// carry-out word.  A lane keeps its whole segment's masks in LDS, so a
+// column is one pass with no barrier and no carry traffic through memory.
+//
+// The LDS table has SIG + 1 planes per quad: plane SIG is all zeros, and a
+// step outside the lane's part of the column (pipeline fill and drain, past
+// the column's end) reads it, which leaves V unchanged and, with a zero
+// carry-in, carries nothing.
+template <int SIG>
+__device__ __forceinline__ uint32_t skew_lds_byte(uint32_t q, uint32_t c, uint32_t lane) {
+  return q * ((SIG + 1) * 1024u) + c * 1024u + lane * 16u;
+}
+
+// Lane l receives lane l - 1's value (lane 0 receives 0).
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+
+// One column through a lanes-per-row group; returns this lane's zero bits.
+// B is the column's symbol stream (16-byte chunks of 8 symbols, nsub = index
+// of its spare chunk); s is the lane's segment index within its row.
+template <int WL, int SIG>
+__device__ __forceinline__ uint32_t skew_column(const uint4* __restrict__ B, uint32_t n, uint32_t L, uint32_t s,
+                                                const char* __restrict__ lbase) {
+  uint32_t V[WL];
+#pragma unroll
+  for (int w = 0; w < WL; ++w) V[w] = 0xFFFFFFFFu;
+  const uint32_t nch = (n + 31u) >> 5;  // 32-symbol chunks
+  const uint32_t nsub = (n + 7u) >> 3;
+  const int32_t last = (int32_t)nch - 1;
+  uint32_t cw = 0;  // carry-out bits of this lane's previous chunk
+  int32_t ci = -(int32_t)s;
+  uint4 nxt = B[min((uint32_t)min(max(ci, 0), max(last, 0)) * 4u, nsub)];
+  for (uint32_t T = 0; T + 1 < nch + L; ++T, ++ci) {
+    uint32_t cin = wave_shr1(cw);
+    if (s == 0) cin = 0u;
+    uint32_t cout = 0u;
+    const uint32_t base = (uint32_t)min(max(ci, 0), max(last, 0)) * 4u;
+    const uint32_t nbase = (uint32_t)min(max(ci + 1, 0), max(last, 0)) * 4u;
+    if (T + 1 >= L && T + 1 < nch) {  // every lane's chunk exists and is full (wave-uniform)
+#pragma unroll 1
+      for (uint32_t x = 0; x < 4; ++x) {
+        const uint4 q = nxt;
+        nxt = B[x < 3 ? base + x + 1 : min(nbase, nsub)];
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.x & 0xFFFFu), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.x >> 16), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.y & 0xFFFFu), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.y >> 16), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.z & 0xFFFFu), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.z >> 16), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.w & 0xFFFFu), cin, cout);
+        long_step<WL, SIG, SIG + 1>(V, lbase + (q.w >> 16), cin, cout);
+      }
+    } else {  // pipeline fill, drain, or the column's last chunk
+#pragma unroll 1
+      for (uint32_t x = 0; x < 4; ++x) {
+        const uint4 q = nxt;
+        nxt = B[min(x < 3 ? base + x + 1 : nbase, nsub)];
+        const int32_t t0 = ci * 32 + (int32_t)(x * 8);  // symbol index of q's first symbol
+        const bool on = ci >= 0;
+        const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t sym = (qw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+          long_step<WL, SIG, SIG + 1>(V, lbase + (on && t0 + k < (int32_t)n ? sym : (uint32_t)SIG * 1024u), cin,
+                                      cout);
+        }
+      }
+    }
+    cw = cout;
+  }
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < WL; ++w) cnt += __builtin_popcount(~V[w]);
+  return cnt;
+}
+
+template <int WL, int WHI, int SIG>
+__device__ __forceinline__ uint32_t skew_column_w(uint32_t wl, const uint4* __restrict__ B, uint32_t n, uint32_t L,
+                                                  uint32_t s, const char* __restrict__ lbase) {
+  if constexpr (WL <= WHI) {
+    if (wl == WL) return skew_column<WL, SIG>(B, n, L, s, lbase);
+    return skew_column_w<WL + 1, WHI, SIG>(wl, B, n, L, s, lbase);
+  } else {
+    return 0;
+  }
+}
+
+// One work item of a lanes-per-row group: stage every lane's segment masks,
+// then waves take columns from an LDS counter.
+template <int SIG>
+__device__ __forceinline__ void skew_item(const DeviceBatch& bt, const LaneDesc* __restrict__ lanes,
+                                          const uint32_t* __restrict__ colmap, const uint64_t* __restrict__ rowbase,
+                                          const GroupDesc& g, const ItemDesc& item, uint32_t sigma, char* lds,
+                                          uint32_t* s_col, int32_t* __restrict__ out) {
+  constexpr uint32_t WHI = SIG == 20 ? 28u : 16u;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t L = g.lpr, WL = (g.W + L - 1u) / L;
+  const uint32_t r = lane / L, s = lane - r * L;
+  const bool on = r < g.nrows;
+  LaneCtx lc{0ull, 0xFFFFFFFFu, 0u, 0u};
+  uint32_t seq = 0;
+  if (on) {
+    const LaneDesc d = lanes[g.lane_first + r];
+    lc.out_off = d.out_off;
+    lc.pos = d.pos;
+    lc.orig = d.orig;
+    seq = d.seq;
+    lc.len = bt.len[seq];
+  }
+  {  // this lane's segment of its row's masks (zero past the row's end and past the segment), and the
+     // zero plane of every quad
+    const uint32_t Q = (WL + 3u) >> 2;
+    const uint32_t Ws = on ? (lc.len + 31u) >> 5 : 0u;
+    const uint64_t mo = on ? bt.mask_off[seq] : 0ull;
+    const uint32_t np = sigma + 1u;
+    for (uint32_t e = wave; e < Q * np; e += nwaves) {
+      const uint32_t q = e / np, c = e - q * np;
+      uint32_t v[4] = {0u, 0u, 0u, 0u};
+      if (c < sigma) {
+        const uint32_t* src = bt.masks + mo + (uint64_t)c * Ws;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+          const uint32_t wl = 4u * q + k, wr = s * WL + wl;
+          v[k] = (wl < WL && wr < Ws) ? src[wr] : 0u;
+        }
+      }
+      const uint32_t plane = c < sigma ? c : (uint32_t)SIG;
+      *reinterpret_cast<uint4*>(lds + skew_lds_byte<SIG>(q, plane, lane)) = make_uint4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  if (threadIdx.x == 0) *s_col = item.c0;
+  __syncthreads();
+  const char* lbase = lds + lane * 16u;
+  for (;;) {
+    uint32_t col = 0;
+    if (lane == 0) col = atomicAdd(s_col, 1u);
+    col = __builtin_amdgcn_readfirstlane(col);
+    if (col >= item.c1) break;
+    uint32_t b = col;
+    uint64_t rb = 0;
+    if (g.colmap_base != kNoMap) {
+      if (col < g.nmap) {
+        b = colmap[g.colmap_base + col];
+        rb = rowbase[g.rowbase_base + col];
+      } else {
+        b = col + g.shift;
+      }
+    }
+    const uint32_t sc = g.fam_base + b;
+    const uint32_t n = bt.len[sc];
+    const uint4* B = reinterpret_cast<const uint4*>(bt.sym + bt.sym_off[sc]);
+    const uint32_t cnt = skew_column_w<kSkewWLMin, WHI, SIG>(WL, B, n, L, s, lbase);
+    uint32_t tot = 0;  // the row's zero bits: the sum over its L lanes
+    for (uint32_t x = 0; x < L; ++x) tot += (uint32_t)__shfl((int)cnt, (int)((r * L + x) & 63u), 64);
+    if (on && s == 0 && col > lc.pos) {
+      const uint64_t o = lc.orig < b ? lc.out_off + (b - lc.orig - 1u) : rb + (lc.orig - b - 1u);
+      out[o] = tile_value(bt.values, tot, lc.len, n);
+    }
+  }
+  __syncthreads();  // LDS and the column counter are reused by the next item
+}
+
 // Rows whose bit vectors exceed the fast classes.  A workgroup takes a work
 // item (group, columns); its waves take one column each per pass, and for
 // every segment of the rows (SEGQ quads) the workgroup stages that segment's
@@ -375,6 +545,7 @@ __global__ __launch_bounds__(1024) void lcs_long_kernel(
   extern __shared__ uint4 lds4[];
   char* lds = reinterpret_cast<char*>(lds4);
   __shared__ uint32_t s_item;
+  __shared__ uint32_t s_col;
   const uint32_t step = ctl->step;
   const uint32_t begin = ranges[step].begin[3];
   const uint32_t end = ranges[step].end[3];
@@ -391,6 +562,10 @@ __global__ __launch_bounds__(1024) void lcs_long_kernel(
     if (it >= end) break;
     const ItemDesc item = items[it];
     const GroupDesc g = groups[item.group];
+    if (g.lpr) {  // lanes-per-row group (uniform for the workgroup)
+      skew_item<SIG>(bt, lanes, colmap, rowbase, g, item, sigma, lds, &s_col, out);
+      continue;
+    }
     uint32_t pos = 0xFFFFFFFFu, orig = 0, seq = 0;
     uint64_t out_off = 0;
     if (lane < g.nrows) {
@@ -614,7 +789,7 @@ static const void* long_kernel_ptr(uint32_t sigma) {
 }
 
 int long_prepare(uint32_t sigma, uint32_t waves, int* blocks_per_cu) {
-  const size_t lds = fast_lds_bytes(sigma, long_seg_q(sigma));
+  const size_t lds = long_lds_bytes(sigma);
   const void* fn = long_kernel_ptr(sigma);
   hipFuncAttributes fa;
   hipError_t e = hipFuncGetAttributes(&fa, fn);
@@ -631,7 +806,7 @@ int long_prepare(uint32_t sigma, uint32_t waves, int* blocks_per_cu) {
 
 int launch_long(const DeviceBatch& b, const DeviceWork& w, StepCtl* ctl, int32_t* out, uint32_t sigma,
                 uint32_t* carry, uint32_t carry_words, uint32_t blocks, uint32_t waves, void* stream) {
-  const size_t lds = fast_lds_bytes(sigma, long_seg_q(sigma));
+  const size_t lds = long_lds_bytes(sigma);
   const dim3 grid(blocks), block(waves * 64);
   if (sig_cap(sigma) == 20)
     hipLaunchKernelGGL((lcs_long_kernel<kLongSegQ[0], 20>), grid, block, lds, (hipStream_t)stream, b, w.groups,

@@ -162,6 +162,8 @@ __global__ __launch_bounds__(kNaPlanThreads) void na_plan_kernel(const uint64_t*
       gd.rowbase_base = 0;
       gd.nmap = k;
       gd.shift = 0;
+      gd.lpr = 0;
+      gd.pad[0] = gd.pad[1] = gd.pad[2] = 0;
       groups[g] = gd;
       const uint32_t ni = (k - P - 1 + C - 1) / C;
       s_first[g] = n;

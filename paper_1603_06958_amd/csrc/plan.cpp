@@ -367,6 +367,63 @@ int famsa_lcs_plan_s::autotune(const char* path) {
       best = cand;
     }
   }
+  // long rows: the lanes-per-row mode at several word widths per lane, or
+  // the segmented kernel, each with 8 or 16 waves per workgroup
+  {
+    std::vector<uint32_t> wls;
+    if (!(opt.flags & FAMSA_LCS_LONG_SEGMENTED))
+      for (uint32_t wl_ : {28u, 24u, 20u, 16u, 12u})
+        if (wl_ <= skew_wl_max(opt.sigma)) wls.push_back(wl_);
+    wls.push_back(0);
+    double best_long = 1e300;
+    LaunchParams lbest = best;
+    DevMem carry;
+    for (uint32_t lw : wls) {
+      LaunchParams cand = best;
+      cand.long_wl = lw;
+      WorkLists w1;
+      build_step(w1, fams, batch.h_len, batch.h_lenprefix, opt.sigma, cand, false);
+      if (!w1.has_long) break;  // the first step has no long rows: nothing to choose
+      int rc;
+      if ((rc = upload(tg, w1.groups, st)) || (rc = upload(tl_, w1.lanes, st)) || (rc = upload(ti, w1.items, st)) ||
+          (rc = upload(tp, w1.prows, st)) || (rc = upload(tc, w1.colmap, st)) || (rc = upload(tr, w1.rowbase, st)) ||
+          (rc = upload(tra, w1.ranges, st)))
+        return rc;
+      const DeviceWork w{tg.as<GroupDesc>(), tl_.as<LaneDesc>(), ti.as<ItemDesc>(), tp.as<PlainRow>(),
+                         tc.as<uint32_t>(), tr.as<uint64_t>(), tra.as<StepRange>()};
+      for (uint32_t wv : {16u, 8u}) {
+        int bpc = 0;
+        if (long_prepare(opt.sigma, wv, &bpc) || bpc == 0) continue;
+        const uint32_t blocks = (uint32_t)bpc * (uint32_t)gi.cus;
+        const uint32_t cw = std::max<uint32_t>(1, (w1.long_col_max + 31) / 32);
+        const uint64_t cbytes = (uint64_t)blocks * wv * cw * 64u * 4u;
+        if (carry.bytes < cbytes && (rc = carry.alloc(cbytes))) return rc;
+        StepCtl hc{};
+        hc.next_step = 0;
+        hc.stride = 1;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          FAMSA_HIP(hipMemcpyAsync(d_ctl.p, &hc, sizeof hc, hipMemcpyHostToDevice, st));
+          if (launch_step_begin(ctl(0), st)) return set_error(FAMSA_LCS_EDEVICE, "step_begin failed");
+          FAMSA_HIP(hipEventRecord(e0, st));
+          if (launch_long(batch.view(), w, ctl(0), d_out[0].as<int32_t>(), opt.sigma, carry.as<uint32_t>(), cw, blocks,
+                          wv, st))
+            return set_error(FAMSA_LCS_EDEVICE, "tuning launch failed");
+          FAMSA_HIP(hipEventRecord(e1, st));
+          FAMSA_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          FAMSA_HIP(hipEventElapsedTime(&ms, e0, e1));
+          best_ms = std::min(best_ms, ms);
+        }
+        if (best_ms < best_long) {
+          best_long = best_ms;
+          lbest = cand;
+          lbest.waves[3] = wv;
+        }
+      }
+    }
+    best = lbest;
+  }
   lp = best;
   int rc;
   if ((rc = tune_store(gi, opt.sigma, lp, path))) return rc;
@@ -542,6 +599,7 @@ int famsa_lcs_plan(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
   if ((rc = gpu_info(o.device, &p->gi))) return fail(rc);
   if (!(o.flags & FAMSA_LCS_NO_AUTOTUNE)) tune_lookup(p->gi, o.sigma, &p->lp);
   if (o.cols_per_item) p->lp.cols_per_item = o.cols_per_item;
+  if (o.flags & FAMSA_LCS_LONG_SEGMENTED) p->lp.long_wl = 0;
 
   // budget: batch + descriptors + 2 step buffers (+ plain scratch)
   size_t freeb = 0, totalb = 0;

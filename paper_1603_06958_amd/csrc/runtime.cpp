@@ -85,7 +85,7 @@ int normalize_options(const famsa_lcs_options* in, Opts* o) {
   if (d.device < 0) return set_error(FAMSA_LCS_EINVAL, "device %d < 0", d.device);
   const uint32_t known = FAMSA_LCS_PLAIN | FAMSA_LCS_DESCENDING | FAMSA_LCS_DEVICE_TILES | FAMSA_LCS_NO_GRAPH |
                          FAMSA_LCS_NO_AUTOTUNE | FAMSA_LCS_ONE_STREAM | FAMSA_LCS_OUT_INDEL | FAMSA_LCS_OUT_SIM |
-                         FAMSA_LCS_PLAIN_ASYNC | FAMSA_LCS_TWO_STREAMS;
+                         FAMSA_LCS_PLAIN_ASYNC | FAMSA_LCS_TWO_STREAMS | FAMSA_LCS_LONG_SEGMENTED;
   if (d.flags & ~known) return set_error(FAMSA_LCS_EINVAL, "unknown flag bits 0x%x", d.flags & ~known);
   if ((d.flags & FAMSA_LCS_OUT_INDEL) && (d.flags & FAMSA_LCS_OUT_SIM))
     return set_error(FAMSA_LCS_EINVAL, "FAMSA_LCS_OUT_INDEL and FAMSA_LCS_OUT_SIM exclude each other");
@@ -234,6 +234,28 @@ int class_of(uint32_t W, uint32_t sigma) {
   return 3;
 }
 
+uint32_t skew_lanes(uint32_t W, uint32_t sigma, const LaunchParams& lp) {
+  if (lp.long_wl == 0) return 0;
+  const uint32_t wmax = std::min(lp.long_wl, skew_wl_max(sigma));
+  if (wmax < kSkewWLMin || W <= wmax) return 0;
+  // L maximising the lanes doing useful work (rows per wave x lanes per row
+  // over 64, the row's dwords over its lanes' dwords) times the share of the
+  // recurrence's 3 WL instructions per step against the 3 per step for the
+  // symbol address and the carry bits
+  double best = 0;
+  uint32_t bl = 0;
+  for (uint32_t L = (W + wmax - 1) / wmax; L <= (uint32_t)kLanes; ++L) {
+    const uint32_t WL = (W + L - 1) / L;
+    if (WL < kSkewWLMin) break;
+    const double u = (double)((kLanes / L) * L) / kLanes * (double)W / (double)(L * WL) * (3.0 * WL) / (3.0 * WL + 3.0);
+    if (u > best + 1e-12) {
+      best = u;
+      bl = L;
+    }
+  }
+  return bl;
+}
+
 namespace {
 struct CostItem {
   uint64_t cost;
@@ -294,10 +316,12 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
       colprefs.emplace_back(k + 1, 0);
       std::vector<uint64_t>& cp = colprefs.back();
       for (uint32_t q = 0; q < k; ++q) cp[q + 1] = cp[q] + len[fb + perm[q]];
-      for (uint32_t P = 0; P + 1 < k; P += kLanes) {
-        const uint32_t nrows = std::min<uint32_t>(kLanes, k - P);
+      for (uint32_t P = 0, nrows = 0; P + 1 < k; P += nrows) {
         const uint32_t W = std::max<uint32_t>(1, (len[fb + perm[P]] + 31) / 32);
+        const uint32_t lpr = class_of(W, sigma) == 3 ? skew_lanes(W, sigma, lp) : 0;
+        nrows = std::min<uint32_t>(lpr ? kLanes / lpr : kLanes, k - P);
         GroupDesc g{};
+        g.lpr = lpr;
         g.lane_first = (uint32_t)wl.lanes.size();
         g.nrows = nrows;
         g.W = W;
@@ -313,7 +337,7 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
           wl.cells[cls] += (uint64_t)len[fb + a] * (cp[k] - cp[P + l + 1]);
           wl.lanes.push_back(ld);
         }
-        if (cls == 3) wl.long_col_max = std::max(wl.long_col_max, len[fb + perm[std::min(P + 1, k - 1)]]);
+        if (cls == 3 && !lpr) wl.long_col_max = std::max(wl.long_col_max, len[fb + perm[std::min(P + 1, k - 1)]]);
         pend.push_back(PendingGroup{g, P + 1, k, cp.data(), 0});
         span += k - (P + 1);
       }
@@ -359,11 +383,13 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
           cp[q + 1] = cp[q] + len[fb + j];
           colmax = std::max(colmax, len[fb + j]);
         }
-        for (uint32_t P = 0; P < ns; P += kLanes) {
-          if (P + 1 >= np) continue;  // only the family's last row: no pairs
-          const uint32_t nrows = std::min<uint32_t>(kLanes, ns - P);
+        for (uint32_t P = 0, nrows = 0; P < ns; P += nrows) {
           const uint32_t W = std::max<uint32_t>(1, (len[fb + rows[ord[P]]] + 31) / 32);
+          const uint32_t lpr = class_of(W, sigma) == 3 ? skew_lanes(W, sigma, lp) : 0;
+          nrows = std::min<uint32_t>(lpr ? kLanes / lpr : kLanes, ns - P);
+          if (P + 1 >= np) continue;  // only the family's last row: no pairs
           GroupDesc g{};
+          g.lpr = lpr;
           g.lane_first = (uint32_t)wl.lanes.size();
           g.nrows = nrows;
           g.W = W;
@@ -379,14 +405,19 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
             wl.cells[cls] += (uint64_t)len[fb + i] * (lenprefix[fb + k] - lenprefix[fb + i + 1]);
             wl.lanes.push_back(ld);
           }
-          if (cls == 3) wl.long_col_max = std::max(wl.long_col_max, colmax);
+          if (cls == 3 && !lpr) wl.long_col_max = std::max(wl.long_col_max, colmax);
           pend.push_back(PendingGroup{g, P + 1, np, cp.data(), 0});
           span += np - (P + 1);
         }
         continue;
       }
-      for (size_t P = 0; P < ord.size(); P += kLanes) {
-        const uint32_t nrows = (uint32_t)std::min<size_t>(kLanes, ord.size() - P);
+      for (size_t P = 0, nrows = 0; P < ord.size(); P += nrows) {
+        uint32_t lpr = 0;
+        if (!plain_only) {  // rows sorted longest first: the first row is the group's widest
+          const uint32_t W0 = std::max<uint32_t>(1, (len[fb + rows[ord[P]]] + 31) / 32);
+          lpr = class_of(W0, sigma) == 3 ? skew_lanes(W0, sigma, lp) : 0;
+        }
+        nrows = (uint32_t)std::min<size_t>(lpr ? kLanes / lpr : kLanes, ord.size() - P);
         uint32_t maxlen = 0, mini = 0xFFFFFFFFu;
         for (uint32_t l = 0; l < nrows; ++l) {
           maxlen = std::max(maxlen, len[fb + rows[ord[P + l]]]);
@@ -401,6 +432,7 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
         g.fam_base = fb;
         g.colmap_base = kNoMap;
         g.rowbase_base = kNoMap;
+        g.lpr = lpr;
         const int cls = plain_only ? 4 : class_of(W, sigma);
         for (uint32_t l = 0; l < nrows; ++l) {
           const uint32_t i = rows[ord[P + l]];
@@ -409,7 +441,7 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
           if (cls < 4) wl.lanes.push_back(ld);
           else add_plain(ld, fb, k, kNoMap, kNoMap);
         }
-        if (cls == 3)
+        if (cls == 3 && !lpr)
           for (uint32_t j = mini + 1; j < k; ++j) wl.long_col_max = std::max(wl.long_col_max, len[fb + j]);
         if (cls < 4) {
           pend.push_back(PendingGroup{g, mini + 1, k, nullptr, lenprefix[fb]});
@@ -442,7 +474,8 @@ void build_step(WorkLists& wl, const std::vector<StepFamily>& fams, const std::v
       uint64_t colsum;
       if (pg.colpref) colsum = pg.colpref[c1] - pg.colpref[c];
       else colsum = lenprefix[pg.g.fam_base + c1] - lenprefix[pg.g.fam_base + c];
-      ci[cls].push_back(CostItem{(uint64_t)pg.g.W * colsum + 64, ItemDesc{gi, c, c1, 0}});
+      const uint64_t wlane = pg.g.lpr ? (pg.g.W + pg.g.lpr - 1) / pg.g.lpr : pg.g.W;  // dwords per lane
+      ci[cls].push_back(CostItem{wlane * colsum + 64, ItemDesc{gi, c, c1, 0}});
     }
   }
   for (int c = 0; c < 4; ++c) {

@@ -97,10 +97,19 @@ struct TileWork {
   uint64_t out_off;      // step-buffer offset of the tile
 };
 
+constexpr uint32_t kLongWlAuto = 0xFFFFFFFFu;
 struct LaunchParams {
   uint32_t waves[4] = {4, 8, 16, 16};  // wavefronts per workgroup per class (3 = long rows)
   uint32_t cols_per_item = 256;
+  // Long rows (class 3): the most dwords a lane holds in the lanes-per-row
+  // mode (which fixes the lanes per row and so the rows per wave), kLongWlAuto
+  // for the largest the LDS allows, 0 for the segmented kernel only.
+  uint32_t long_wl = kLongWlAuto;
 };
+
+// Lanes per row for a long row of W dwords in the lanes-per-row mode, 0 when
+// the row goes to the segmented kernel (mode off, or W beyond 64 lanes).
+uint32_t skew_lanes(uint32_t W, uint32_t sigma, const LaunchParams& lp);
 
 // The launches one step needs: for each fast class the quad count of its
 // widest group (0: no items), and whether long-row items and plain rows
@@ -127,8 +136,8 @@ struct WorkLists {
   std::vector<StepRange> ranges;
   std::vector<StepSig> sigs;       // per step
   uint32_t qmax[3] = {0, 0, 0};   // largest mask quad count per fast class
-  bool has_long = false;           // items for the segmented long-row kernel
-  uint32_t long_col_max = 0;       // longest column a long-row item streams
+  bool has_long = false;           // items for the long-row kernel (segmented or lanes per row)
+  uint32_t long_col_max = 0;       // longest column a segmented long-row item streams
   uint32_t w64max_plain = 0;       // largest ceil(len/64) in plain rows
   uint64_t cells[5] = {0, 0, 0, 0, 0};
   uint64_t max_plain_pairs = 0;

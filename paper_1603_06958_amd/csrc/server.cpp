@@ -311,6 +311,7 @@ int famsa_lcs_server_create(const famsa_lcs_options* opt, famsa_lcs_server_t** o
   if ((rc = gpu_info(o.device, &s->gi))) return rc;
   if (!(o.flags & FAMSA_LCS_NO_AUTOTUNE)) tune_lookup(s->gi, o.sigma, &s->lp);
   if (o.cols_per_item) s->lp.cols_per_item = o.cols_per_item;
+  if (o.flags & FAMSA_LCS_LONG_SEGMENTED) s->lp.long_wl = 0;
   size_t freeb = 0, totalb = 0;
   FAMSA_HIP(hipMemGetInfo(&freeb, &totalb));
   s->budget = o.hbm_budget ? o.hbm_budget : (uint64_t)(freeb * 0.9);

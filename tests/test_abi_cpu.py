@@ -93,7 +93,7 @@ def test_options_layout_and_older_callers():
 
 def test_einval_options():
     assert plan_rc([0], [0, 1], tile_rows=0)[0] == B.EINVAL
-    assert plan_rc([0], [0, 1], flags=0x400)[0] == B.EINVAL
+    assert plan_rc([0], [0, 1], flags=0x800)[0] == B.EINVAL
     rc, msg = plan_rc([0], [0, 1], flags=B.ONE_STREAM | B.TWO_STREAMS)
     assert rc == B.EINVAL and "exclude" in msg
     rc, msg = plan_rc([0], [0, 1], flags=B.OUT_INDEL | B.OUT_SIM)

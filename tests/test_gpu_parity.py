@@ -177,3 +177,39 @@ def test_torch_stream_and_repeat():
     for key in t1:
         assert np.array_equal(t1[key], t2[key])
     check_all_tiles(b, t1, 1024)
+
+
+def long_rows_family(seed, sigma, k, lo, hi):
+    rng = np.random.default_rng(seed)
+    lens = list(rng.integers(lo, hi + 1, k))
+    lens[:6] = [hi, hi, lo, 897, 1791, 1792][:6]
+    seqs = [rng.integers(0, sigma, int(L)).astype(np.uint8) for L in lens]
+    seqs[5] = seqs[0].copy()                     # identical long rows
+    seqs += [np.full(3000, sigma - 1, np.uint8), np.zeros(0, np.uint8), np.full(40, sigma - 1, np.uint8)]
+    return inputs.from_sequences(seqs, name=f"long{sigma}")
+
+
+@pytest.mark.parametrize("sigma,lo,hi", [(20, 800, 3100), (32, 400, 2100), (2, 850, 2000)])
+@pytest.mark.parametrize("tile_rows", [1024, 7])
+def test_long_rows_lanes_per_row_and_segmented(sigma, lo, hi, tile_rows):
+    # rows longer than one lane holds: the lanes-per-row mode (default) and
+    # the segmented kernel both give the oracle's values, in family mode and
+    # tile mode
+    b = long_rows_family(61 + sigma, sigma, 70, lo, hi)
+    a = max(sigma, 2)
+    t_lpr, _, st = run(b, alphabet_size=a, tile_rows=tile_rows)
+    assert st.cells[3] > 0  # long rows ran in the long-row kernel
+    check_all_tiles(b, t_lpr, tile_rows)
+    t_seg, _, _ = run(b, alphabet_size=a, tile_rows=tile_rows, flags=B.LONG_SEGMENTED)
+    assert t_seg.keys() == t_lpr.keys()
+    assert all(np.array_equal(t_seg[key], t_lpr[key]) for key in t_lpr)
+
+
+def test_long_rows_autotuned_word_width():
+    # the tuner searches the long rows' word width per lane (and the
+    # segmented kernel); whatever it picks, values equal the oracle's
+    b = long_rows_family(70, 20, 90, 900, 2500)
+    with B.Plan.from_batch(b, flags=B.NO_GRAPH) as p:
+        p.autotune(None)
+        tiles = p.collect()
+    check_all_tiles(b, tiles, 1024)

@@ -85,3 +85,25 @@ def test_tile_mode_walks_no_column_below_its_rows(opt):
         pos = L[g["lane_first"]:g["lane_first"] + g["nrows"]]["pos"].astype(np.int64)
         assert np.array_equal(pos, pos[0] + np.arange(g["nrows"]))
         assert first_c0[gi] == pos[0] + 1
+
+
+@pytest.mark.parametrize("name,sigma,wlmax", [("edges_family", 20, 28), ("edges_tile5", 20, 28), ("sigma32", 32, 16)])
+def test_lanes_per_row_groups(name, sigma, wlmax):
+    # long rows spread over several lanes: the rows of a group and their
+    # lanes fit one wave, each lane holds between 8 and the LDS limit of
+    # dwords, the group's widest row fits its lanes, and such groups exist
+    make, opt = CASES[name]
+    b = make()
+    d, _ = dry_run(b, **opt)
+    g = d["groups"]
+    skew = g[g["lpr"] > 0]
+    assert len(skew) > 0
+    L = skew["lpr"].astype(np.int64)
+    wl = (skew["W"].astype(np.int64) + L - 1) // L
+    assert (skew["nrows"] * L <= 64).all()
+    assert ((wl >= 8) & (wl <= wlmax)).all()
+    assert (wl * L >= skew["W"]).all()
+    lens = b.lengths()
+    for gr in skew:
+        ln = d["lanes"][gr["lane_first"]:gr["lane_first"] + gr["nrows"]]
+        assert ((lens[ln["seq"]] + 31) // 32 <= gr["W"]).all()

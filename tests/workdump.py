@@ -16,7 +16,8 @@ DT = {
     "steps": np.dtype([("tile_begin", "<u8"), ("tile_end", "<u8"), ("values", "<u8")]),
     "ranges": np.dtype([("begin", "<u4", 5), ("end", "<u4", 5), ("plain_pairs", "<u8")]),
     "groups": np.dtype([("lane_first", "<u4"), ("nrows", "<u4"), ("W", "<u4"), ("fam_base", "<u4"),
-                        ("colmap_base", "<u4"), ("rowbase_base", "<u4"), ("nmap", "<u4"), ("shift", "<u4")]),
+                        ("colmap_base", "<u4"), ("rowbase_base", "<u4"), ("nmap", "<u4"), ("shift", "<u4"),
+                        ("lpr", "<u4"), ("pad", "<u4", 3)]),
     "lanes": np.dtype([("out_off", "<u8"), ("seq", "<u4"), ("pos", "<u4"), ("orig", "<u4"), ("pad", "<u4")]),
     "items": np.dtype([("group", "<u4"), ("c0", "<u4"), ("c1", "<u4"), ("pad", "<u4")]),
     "prows": np.dtype([("out_off", "<u8"), ("pair_first", "<u8"), ("seq", "<u4"), ("pos", "<u4"), ("orig", "<u4"),
