@@ -109,6 +109,10 @@ typedef struct famsa_lcs_plan_s famsa_lcs_plan_t;
 /*
  * Validate the batch, copy it to the device, build the per-symbol match
  * bit masks and the work lists, allocate tile buffers, and return a plan.
+ * The quantity a plan computes is the one the first stage of the method
+ * defines (Methods, "Pairwise similarities calculation"): the length of a
+ * longest common subsequence of every pair of sequences of a family, found
+ * bit-parallel, w DP cells per machine word.
  *   codes      nseq sequences back to back (may be NULL if all are empty)
  *   seq_off    nseq + 1 non-decreasing offsets into codes
  *   fam_off    nfam + 1 non-decreasing offsets into the sequence list with
@@ -143,7 +147,10 @@ typedef int (*famsa_lcs_tile_fn)(void* user, const famsa_lcs_tile* tile);
 
 /*
  * Compute and deliver every tile with index >= first_tile, in order, calling
- * fn(user, tile) on the calling thread.  The tile memory is valid only during
+ * fn(user, tile) on the calling thread.  Tiles are streamed so a consumer
+ * can build the single-linkage guide tree as the similarities arrive,
+ * without the k x k matrix (Methods, "Determination of the guide tree":
+ * the first two stages run together in O(k) memory).  The tile memory is valid only during
  * the callback.  While a callback runs, the next tiles are being computed.
  * Errors: EINVAL (NULL plan/fn, first_tile > tile count), EBUSY (plan in
  * use, e.g. called from inside its own callback), ECANCELED, EDEVICE.
@@ -151,7 +158,9 @@ typedef int (*famsa_lcs_tile_fn)(void* user, const famsa_lcs_tile* tile);
  */
 int famsa_lcs_tiles(famsa_lcs_plan_t* plan, uint64_t first_tile, famsa_lcs_tile_fn fn, void* user);
 
-/* Free everything the plan holds.  NULL is a no-op. */
+/* Free everything the plan holds (its device batch, masks, work lists and
+ * tile buffers: the memory of the first stage of the method, Methods,
+ * "Determination of the guide tree").  NULL is a no-op. */
 void famsa_lcs_release(famsa_lcs_plan_t* plan);
 
 /* Thread-local text of the last error ("" if none). */

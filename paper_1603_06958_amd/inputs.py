@@ -219,24 +219,35 @@ class ServeJob:
     batch: Batch
 
 
+def _c5_job(args) -> Batch:
+    j, ss, k_range, root_range, k_scale, seed = args
+    rng = np.random.default_rng(ss)
+    k = _log_uniform_int(rng, *k_range)
+    L = _log_uniform_int(rng, *root_range)
+    k = max(2, int(round(k * k_scale)))
+    return from_sequences(evolve_family(k, L, rng), name=f"c5job{j}", seed=seed)
+
+
 def c5(seed: int = 4, njobs: int = 200, rate_per_s: float = 2.0, k_range=(100, 20000),
-       root_range=(50, 1500), k_scale: float = 1.0) -> List[ServeJob]:
+       root_range=(50, 1500), k_scale: float = 1.0, workers: int = 0) -> List[ServeJob]:
     """Serving jobs with Poisson arrivals at ``rate_per_s`` jobs per second.
 
     ``k_scale`` shrinks every family size (k -> max(2, round(k * k_scale)))
-    so the same arrival stream can be replayed at a smaller cost.
+    so the same arrival stream can be replayed at a smaller cost.  Each job
+    draws from its own spawned seed, so ``workers`` > 1 (processes building
+    jobs in parallel) gives the same jobs.
     """
     root = np.random.SeedSequence(seed)
     s_arr, s_jobs = root.spawn(2)
     arr = np.cumsum(np.random.default_rng(s_arr).exponential(1.0 / rate_per_s, njobs))
-    jobs = []
-    for j, ss in enumerate(s_jobs.spawn(njobs)):
-        rng = np.random.default_rng(ss)
-        k = _log_uniform_int(rng, *k_range)
-        L = _log_uniform_int(rng, *root_range)
-        k = max(2, int(round(k * k_scale)))
-        jobs.append(ServeJob(float(arr[j]), from_sequences(evolve_family(k, L, rng), name=f"c5job{j}", seed=seed)))
-    return jobs
+    args = [(j, ss, k_range, root_range, k_scale, seed) for j, ss in enumerate(s_jobs.spawn(njobs))]
+    if workers > 1 and njobs > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, njobs)) as pool:
+            batches = pool.map(_c5_job, args, chunksize=1)
+    else:
+        batches = [_c5_job(a) for a in args]
+    return [ServeJob(float(arr[j]), b) for j, b in enumerate(batches)]
 
 
 def random_family(k: int, lo: int, hi: int, seed: int, alphabet: int = ALPHABET) -> Batch:

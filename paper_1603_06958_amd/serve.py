@@ -18,9 +18,9 @@ from . import binding as B
 from . import inputs
 
 # Arrival rate for the c5 serving workload, in jobs per second: 0.7 x the
-# saturated job throughput measured on one MI355X (c5 job mix, full k range:
-# 40 jobs in 0.84 s, 47.6 jobs/s).
-C5_RATE_PER_S = 33.3
+# saturated job throughput measured on one MI355X (the 200-job c5 mix replayed
+# at once: 2.95 s, 67.8 jobs/s).
+C5_RATE_PER_S = 47.5
 
 
 class Server:
@@ -172,12 +172,30 @@ def alone_ms(jobs: List[inputs.ServeJob], **server_opts) -> np.ndarray:
     return out
 
 
-def run_c5_bench(njobs: int = 40, rate: float = C5_RATE_PER_S, seed: int = 4) -> Dict:
-    jobs = inputs.c5(seed=seed, njobs=njobs, rate_per_s=rate)
+def _summary(r: Dict) -> Dict:
+    return {k: r[k] for k in ("jobs", "wall_s", "pairs_per_s", "gcups", "p50_ms", "p99_ms", "max_ms",
+                              "max_jobs_per_step")}
+
+
+def run_c5_bench(njobs: int = 200, rate: float = C5_RATE_PER_S, seed: int = 4, loads=(0.5, 0.7, 0.9),
+                 workers: int = 16) -> Dict:
+    """The serving workload: `njobs` jobs at the frozen arrival rate, the same
+    jobs replayed at once (saturated: the capacity in jobs/s), and at each of
+    `loads` times that capacity (arrival times rescaled)."""
+    import dataclasses
+    import os
+    try:
+        workers = max(1, min(workers, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        workers = 1
+    jobs = inputs.c5(seed=seed, njobs=njobs, rate_per_s=rate, workers=workers)
     opts = dict(step_values=SERVE_STEP_VALUES, step_cells=SERVE_STEP_CELLS, tile_rows=SERVE_TILE_ROWS)
+    sat = run_jobs(jobs, realtime=False, **opts)
+    capacity = njobs / sat["wall_s"]
     r = run_jobs(jobs, **opts)
     lat = r.pop("latencies_ms")
     ids = r.pop("job_ids")
+    r.pop("step_jobs")
     # latency over the job's own service time alone: job cost spans orders of
     # magnitude, so this says how much waiting the mix added to each job
     alone = alone_ms(jobs, **opts)
@@ -188,6 +206,14 @@ def run_c5_bench(njobs: int = 40, rate: float = C5_RATE_PER_S, seed: int = 4) ->
     r["workload"] = (f"c5: {njobs} jobs, Poisson arrivals at {rate} jobs/s, each a tree-evolved family with k "
                      f"log-uniform [100,20000] and root length log-uniform [50,1500], seed {seed}")
     r["arrival_rate_per_s"] = rate
+    r["saturated"] = dict(_summary(sat), capacity_jobs_per_s=round(capacity, 2))
+    r["load_sweep"] = {}
+    for load in loads:
+        lam = load * capacity
+        scaled = [dataclasses.replace(j, arrival_s=j.arrival_s * rate / lam) for j in jobs]
+        x = run_jobs(scaled, **opts)
+        r["load_sweep"][str(load)] = dict(_summary(x), arrival_rate_per_s=round(lam, 2))
+    r["frozen_rate_load"] = round(rate / capacity, 3)
     r["step_values"] = SERVE_STEP_VALUES
     r["step_cells"] = SERVE_STEP_CELLS
     r["tile_rows"] = SERVE_TILE_ROWS
