@@ -158,9 +158,17 @@ __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict
   }
 }
 
-__device__ __forceinline__ int64_t shfl_up64(int64_t v) {
-  const int32_t lo = __shfl_up((int32_t)(uint32_t)(uint64_t)v, 1, 64);
-  const int32_t hi = __shfl_up((int32_t)(uint32_t)((uint64_t)v >> 32), 1, 64);
+// Lane l receives lane l - 1's value (DPP wave shift; lane 0 keeps its own).
+__device__ __forceinline__ int64_t shr1_64(int64_t v) {
+  const int lo = (int)(uint32_t)(uint64_t)v, hi = (int)(uint32_t)((uint64_t)v >> 32);
+  const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
+  return (int64_t)(((uint64_t)b << 32) | a);
+}
+
+__device__ __forceinline__ int64_t shfl_up64(int64_t v, int d) {
+  const int32_t lo = __shfl_up((int32_t)(uint32_t)(uint64_t)v, d, 64);
+  const int32_t hi = __shfl_up((int32_t)(uint32_t)((uint64_t)v >> 32), d, 64);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
@@ -193,23 +201,30 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
   int64_t* edge = A.edge + P.edge;  // [j][M, D, I] of the row above the current strip
   uint8_t* dir = A.dir + P.dir;
   uint8_t* strips = dir + pdp_row0_bytes(n);
-  // row 0: gaps in the sequence before its first residue (terminal costs)
-  if (lane == 0) {
-    int64_t Mp = 0, Dp = kNeg, Ip = kNeg;
-    for (uint32_t j = 0; j <= n; ++j) {
-      int64_t M = kNeg, D = kNeg, b;
-      const int64_t I = kNeg;
-      int ds = 0;
-      if (j == 0) M = 0;
-      else ds = argmax3(Mp - dto[j - 1], Ip - dto[j - 1], Dp - dte[j - 1], &D);
-      const int bk = argmax3(M, D, I, &b);
-      dir[j] = (uint8_t)(bk | (ds << 2));
-      edge[3 * j] = M;
-      edge[3 * j + 1] = D;
-      edge[3 * j + 2] = I;
-      Mp = M;
-      Dp = D;
-      Ip = I;
+  // row 0: gaps in the sequence before its first residue (terminal costs).
+  // M(0,0) = 0 and D(0,1) comes from it; D(0,j), j >= 2, extends D(0,j-1);
+  // every other candidate starts from the unreachable value, far below any
+  // reachable one within the library's input limits, so row 0 is a prefix
+  // sum, taken 64 columns at a time across the lanes.
+  {
+    int64_t carry = 0;  // D(0, base - 1)
+    for (uint32_t base = 0; base <= n; base += 64) {
+      const uint32_t j = base + lane;
+      int64_t x = 0;
+      if (j >= 1 && j <= n) x = j == 1 ? -dto[0] : -dte[j - 1];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = shfl_up64(x, d);
+        if ((int)lane >= d) x += y;
+      }
+      const int64_t Dj = carry + x;
+      if (j <= n) {
+        edge[3 * j] = j == 0 ? 0 : kNeg;
+        edge[3 * j + 1] = j == 0 ? kNeg : Dj;
+        edge[3 * j + 2] = kNeg;
+        dir[j] = (uint8_t)(j == 0 ? 0u : (1u | ((j == 1 ? 0u : 2u) << 2)));
+      }
+      carry = bcast64(Dj, 63);
     }
   }
   __threadfence_block();
@@ -227,22 +242,43 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
     uint8_t* dstrip = strips + (uint64_t)(i0 >> 6) * pdp_strip_bytes(n) + lane;
     int64_t diag = kNeg;
     Mc = Dc = Ic = kNeg;
-    for (uint32_t t = 0; t < n + 64; ++t) {
-      int64_t Mu = shfl_up64(Mc), Du = shfl_up64(Dc), Iu = shfl_up64(Ic);
-      const int32_t j = (int32_t)t - (int32_t)lane;
-      if (lane == 0 && j <= (int32_t)n) {
-        Mu = edge[3 * j];
-        Du = edge[3 * j + 1];
-        Iu = edge[3 * j + 2];
+    // this lane's column values, loaded one step ahead: column j = t - lane
+    int64_t c_cost = 0, c_po = 0, c_pe = 0, c_if = 0, c_ie = 0, e_M = 0, e_D = 0, e_I = 0;
+    auto fetch = [&](int32_t jj) {
+      if (jj >= 1 && jj <= (int32_t)n) {
+        c_cost = crow[jj - 1];
+        c_po = po[jj - 1];
+        c_pe = pe[jj - 1];
       }
+      if (jj >= 0 && jj <= (int32_t)n) {
+        c_if = ifirst[jj];
+        c_ie = iext[jj];
+        if (lane == 0) {
+          e_M = edge[3 * jj];
+          e_D = edge[3 * jj + 1];
+          e_I = edge[3 * jj + 2];
+        }
+      }
+    };
+    fetch(-(int32_t)lane);
+    for (uint32_t t = 0; t < n + 64; ++t) {
+      int64_t Mu = shr1_64(Mc), Du = shr1_64(Dc), Iu = shr1_64(Ic);
+      const int32_t j = (int32_t)t - (int32_t)lane;
+      if (lane == 0) {
+        Mu = e_M;
+        Du = e_D;
+        Iu = e_I;
+      }
+      const int64_t cost = c_cost, o = c_po, e = c_pe, f = c_if, x = c_ie;
+      fetch(j + 1);
       if (active && j >= 0 && j <= (int32_t)n) {
         int64_t M = kNeg, D = kNeg, I, b;
         int ds = 0;
         if (j >= 1) {
-          M = diag + (int64_t)crow[j - 1];
-          ds = argmax3(Mc - po[j - 1], Ic - po[j - 1], Dc - pe[j - 1], &D);
+          M = diag + cost;
+          ds = argmax3(Mc - o, Ic - o, Dc - e, &D);
         }
-        const int is = argmax3(Mu - ifirst[j], Du - ifirst[j], Iu - iext[j], &I);
+        const int is = argmax3(Mu - f, Du - f, Iu - x, &I);
         const int bk = argmax3(M, D, I, &b);
         dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
         argmax3(Mu, Du, Iu, &diag);  // the cell above is the next column's diagonal
