@@ -414,6 +414,8 @@ def main():
                     help="only run a plain device copy of 1 GiB (for scaling HBM byte counters)")
     ap.add_argument("--peak", action="store_true",
                     help="only run the integer-VALU ceiling microbenchmark (all four instruction variants)")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="only run the c3 batching measurement (batched, plain, plain-async)")
     ap.add_argument("--profile-dp", action="store_true",
                     help="only run the sequence-to-profile alignment measurement")
     ap.add_argument("--consumer-alone", action="store_true",
@@ -430,6 +432,9 @@ def main():
         return
     if a.peak:
         print(json.dumps({"valu_peak": run_peak(variants=(0, 1, 2, 3))}), flush=True)
+        return
+    if a.c3_only:
+        print(json.dumps({"c3": run_c3()}), flush=True)
         return
     if a.profile_dp:
         print(json.dumps({"profile_dp": run_profile_dp()}), flush=True)
