@@ -82,10 +82,8 @@ __global__ void step_begin_kernel(StepCtl* ctl) {
 // every symbol c, the 64 lanes' 16-byte quads lie side by side:
 //   byte offset = q * SIG * 1024 + c * 1024 + lane * 16.
 // A wave's 128-bit read of one (q, c) plane is 1 KB of consecutive bytes,
-// conflict free (a partial last quad is read as 32/64/96 bits at the same
-// 16-byte lane stride, which conflicts), and the symbol's part c * 1024 does
-// not depend on W, so the column streams store it pre-scaled and one SDWA
-// v_add forms the address.
+// conflict free, and the symbol's part c * 1024 does not depend on W, so the
+// column streams store it pre-scaled and one SDWA v_add forms the address.
 template <int SIG>
 __device__ __forceinline__ uint32_t lds_byte(uint32_t q, uint32_t c, uint32_t lane) {
   return q * (SIG * 1024u) + c * 1024u + lane * 16u;
