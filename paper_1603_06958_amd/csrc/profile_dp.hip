@@ -18,7 +18,8 @@
 //                      gap column inserted into the profile there, from the
 //                      counts of rows in each of the four situations
 //                      (terminal or inside, next to a gap or opening one);
-//   pdp_dp_kernel   -- a wave per problem: the three-state DP
+//   pdp_dp_kernel   -- a workgroup of up to four waves per problem: the
+//                      three-state DP
 //                        M(i,j) = best(i-1,j-1) + cost[a_i][j]
 //                        D(i,j) = max(M - o w_j, I - o w_j, D - e w_j)(i,j-1)
 //                        I(i,j) = max(M - f_j, D - f_j, I - x_j)(i-1,j)
@@ -27,9 +28,11 @@
 //                      column t - l, takes the cell above from lane l - 1
 //                      (and lane 0 from the strip above's last row, kept in
 //                      global memory), and records the three choices of each
-//                      cell in one byte; then the wave traces one optimal
-//                      alignment back from (m, n), staging 64 steps of
-//                      choices in LDS at a time.
+//                      cell in one byte; consecutive strips run on different
+//                      waves, each a fixed number of steps behind the strip
+//                      above, in phases separated by barriers; then the
+//                      alignment is traced back from (m, n), staging 64 steps
+//                      of choices in LDS at a time.
 // Ties take the first maximum in the order written (M, D, I), as a fixed
 // rule, so the alignment and not only its score is unique.  All DP
 // arithmetic is int64.
@@ -48,7 +51,6 @@ namespace famsa {
 namespace {
 
 constexpr uint8_t kGap = FAMSA_PROFILE_GAP;
-constexpr int64_t kNeg = INT64_MIN / 4;
 double g_profile_dp_ms = 0;  // duration of the last batch's DP launch
 
 struct PdpProb {        // one problem's offsets into the batch arrays
@@ -57,10 +59,11 @@ struct PdpProb {        // one problem's offsets into the batch arrays
   uint64_t cost;        // cost (int32), sigma x n
   uint64_t col;         // w (int32, n); dgap (int64, 4 n); ifirst, iext (int64, n + 1)
   uint64_t rowx;        // first, last (int32, K)
-  uint64_t edge;        // edge (int64, 3 (n + 1))
+  uint64_t edge;        // edge (int64, 2 buffers of 3 (n + 1))
   uint64_t dir;         // dir (bytes): row 0, then strips of (n + 64) x 64
   uint64_t ops;         // ops (bytes), m + n
-  uint32_t m, n, K, pad;
+  uint32_t m, n, K;
+  uint32_t narrow;      // 1: every DP value fits 28 bits, so the DP runs in int32
 };
 
 struct PdpArrays {
@@ -80,9 +83,10 @@ struct PdpArrays {
   uint32_t* nops;
 };
 
-__device__ __forceinline__ int argmax3(int64_t x0, int64_t x1, int64_t x2, int64_t* best) {
+template <typename T>
+__device__ __forceinline__ int argmax3(T x0, T x1, T x2, T* best) {
   int k = 0;
-  int64_t b = x0;
+  T b = x0;
   if (x1 > b) { b = x1; k = 1; }
   if (x2 > b) { b = x2; k = 2; }
   *best = b;
@@ -159,7 +163,10 @@ __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict
 }
 
 // Lane l receives lane l - 1's value (DPP wave shift; lane 0 keeps its own).
-__device__ __forceinline__ int64_t shr1_64(int64_t v) {
+__device__ __forceinline__ int32_t shr1(int32_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int64_t shr1(int64_t v) {
   const int lo = (int)(uint32_t)(uint64_t)v, hi = (int)(uint32_t)((uint64_t)v >> 32);
   const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
   const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
@@ -187,18 +194,155 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, uint32_t src) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ probs, PdpArrays A) {
-  __shared__ uint4 stage4[256];  // 4 KB window of choice bytes
-  const uint8_t* stage = reinterpret_cast<const uint8_t*>(stage4);
-  const PdpProb P = probs[blockIdx.x];
-  const uint32_t lane = threadIdx.x, m = P.m, n = P.n;
+// Several waves per problem.  Strip s (rows 64 s + 1 .. 64 s + 64) runs its
+// sweep steps [q C, (q + 1) C) in phase 2 s + q on wave s mod nw.  Lane 0 of
+// strip s reads, at step t, the edge value lane 63 of strip s - 1 wrote at
+// its step t + 63, which the two-phase lag with C >= 64 makes an earlier
+// phase; C >= (n + 64) / (2 nw) keeps a wave's strips apart in time.  Phases
+// end at a barrier.  Strip s reads edge buffer (s + 1) mod 2 and writes
+// buffer s mod 2 (row 0 is buffer 1): strip s + 2 overwrites a column of
+// buffer s mod 2 two phases after strip s + 1 has read it.
+constexpr uint32_t kPdpWaves = 4;
+
+// The unreachable value of each value type: far enough below every reachable
+// value (|value| < 2^28 for int32, < 2^58 for int64 within the input limits)
+// that subtracting a cost from it never overflows or wins a maximum.
+template <typename T>
+__host__ __device__ constexpr T pdp_neg();
+template <>
+__host__ __device__ constexpr int32_t pdp_neg<int32_t>() { return INT32_MIN / 4; }
+template <>
+__host__ __device__ constexpr int64_t pdp_neg<int64_t>() { return INT64_MIN / 4; }
+
+// The strips of one problem in value type T (int32 when every value fits
+// 28 bits, else int64); phases as described above.  Edge rows and the final
+// cell are kept as int64 holding T values.
+template <typename T>
+__device__ __forceinline__ void pdp_strips(const PdpProb& P, const PdpArrays& A, uint32_t nw, int64_t* s_fin) {
+  constexpr T neg = pdp_neg<T>();
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, m = P.m, n = P.n;
+  const uint32_t S = (m + 63u) >> 6;
   const int64_t* dto = A.dgap + 4 * P.col;
   const int64_t* dte = dto + n;
   const int64_t* dgo = dto + 2 * n;
   const int64_t* dge = dto + 3 * n;
   const int64_t* ifirst = A.ifirst + P.col;
   const int64_t* iext = A.iext + P.col;
-  int64_t* edge = A.edge + P.edge;  // [j][M, D, I] of the row above the current strip
+  int64_t* edges = A.edge + P.edge;
+  const uint64_t ebuf = 3ull * (n + 1);
+  uint8_t* strips = A.dir + P.dir + pdp_row0_bytes(n);
+  const uint32_t steps = n + 64;
+  const uint32_t C = max(64u, (steps + 2 * nw - 1) / (2 * nw));
+  const uint32_t Q = (steps + C - 1) / C;
+  const uint32_t nphase = S ? 2 * (S - 1) + Q : 0;
+  // this wave's current strip
+  T Mc = neg, Dc = neg, Ic = neg, diag = neg;
+  T c_cost = 0, c_po = 0, c_pe = 0, c_if = 0, c_ie = 0, e_M = 0, e_D = 0, e_I = 0;
+  bool active = false, writes_edge = false;
+  const int64_t* po = dgo;
+  const int64_t* pe = dge;
+  const int32_t* crow = A.cost + P.cost;
+  const int64_t* ein = edges;
+  int64_t* eout = edges;
+  uint8_t* dstrip = strips;
+  auto fetch = [&](int32_t jj) {
+    if (jj >= 1 && jj <= (int32_t)n) {
+      c_cost = (T)crow[jj - 1];
+      c_po = (T)po[jj - 1];
+      c_pe = (T)pe[jj - 1];
+    }
+    if (jj >= 0 && jj <= (int32_t)n) {
+      c_if = (T)ifirst[jj];
+      c_ie = (T)iext[jj];
+      if (lane == 0) {
+        e_M = (T)ein[3 * jj];
+        e_D = (T)ein[3 * jj + 1];
+        e_I = (T)ein[3 * jj + 2];
+      }
+    }
+  };
+  for (uint32_t p = 0; p < nphase; ++p) {
+    if (p >= 2 * wave) {
+      const uint32_t s = wave + nw * ((p / 2 - wave) / nw);  // latest strip of this wave started by phase p
+      if (s < S && p < 2 * s + Q) {
+        const uint32_t q = p - 2 * s;
+        if (q == 0) {  // a new strip
+          const uint32_t i = 64 * s + 1 + lane;
+          active = i <= m;
+          const bool terminal = i == m;  // gaps after the sequence's last residue
+          po = terminal ? dto : dgo;
+          pe = terminal ? dte : dge;
+          const uint32_t a = active ? A.seqs[P.seq + i - 1] : 0u;
+          crow = A.cost + P.cost + (uint64_t)a * n;
+          writes_edge = lane == 63 && s + 1 < S;
+          ein = edges + ((s + 1) & 1u) * ebuf;
+          eout = edges + (s & 1u) * ebuf;
+          dstrip = strips + (uint64_t)s * pdp_strip_bytes(n) + lane;
+          Mc = Dc = Ic = diag = neg;
+          fetch(-(int32_t)lane);
+        }
+        const uint32_t t1 = min((q + 1) * C, steps);
+        for (uint32_t t = q * C; t < t1; ++t) {
+          T Mu = shr1(Mc), Du = shr1(Dc), Iu = shr1(Ic);
+          const int32_t j = (int32_t)t - (int32_t)lane;
+          if (lane == 0) {
+            Mu = e_M;
+            Du = e_D;
+            Iu = e_I;
+          }
+          const T cost = c_cost, o = c_po, e = c_pe, f = c_if, x = c_ie;
+          fetch(j + 1);
+          if (active && j >= 0 && j <= (int32_t)n) {
+            T M = neg, D = neg, I, b;
+            int ds = 0;
+            if (j >= 1) {
+              M = diag + cost;
+              ds = argmax3(Mc - o, Ic - o, Dc - e, &D);
+            }
+            const int is = argmax3(Mu - f, Du - f, Iu - x, &I);
+            const int bk = argmax3(M, D, I, &b);
+            dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
+            argmax3(Mu, Du, Iu, &diag);  // the cell above is the next column's diagonal
+            Mc = M;
+            Dc = D;
+            Ic = I;
+            if (writes_edge) {
+              eout[3 * j] = (int64_t)M;
+              eout[3 * j + 1] = (int64_t)D;
+              eout[3 * j + 2] = (int64_t)I;
+            }
+          }
+        }
+        if (s + 1 == S && t1 == steps && lane == ((m - 1) & 63u)) {  // the cell (m, n)
+          s_fin[0] = (int64_t)Mc;
+          s_fin[1] = (int64_t)Dc;
+          s_fin[2] = (int64_t)Ic;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+
+__global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* __restrict__ probs, PdpArrays A) {
+  __shared__ uint4 stage4[256];  // 4 KB window of choice bytes
+  __shared__ int64_t s_fin[3];
+  const uint8_t* stage = reinterpret_cast<const uint8_t*>(stage4);
+  const PdpProb P = probs[blockIdx.x];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, m = P.m, n = P.n;
+  const uint32_t S = (m + 63u) >> 6;  // strips
+  const uint32_t nw = max(1u, min(kPdpWaves, S));
+  if (wave >= nw) return;  // surplus waves leave; barriers wait for the waves that remain
+  const int64_t* dto = A.dgap + 4 * P.col;
+  const int64_t* dte = dto + n;
+  const int64_t* dgo = dto + 2 * n;
+  const int64_t* dge = dto + 3 * n;
+  const int64_t* ifirst = A.ifirst + P.col;
+  const int64_t* iext = A.iext + P.col;
+  int64_t* edges = A.edge + P.edge;  // two buffers of [j][M, D, I]
+  const uint64_t ebuf = 3ull * (n + 1);
   uint8_t* dir = A.dir + P.dir;
   uint8_t* strips = dir + pdp_row0_bytes(n);
   // row 0: gaps in the sequence before its first residue (terminal costs).
@@ -206,8 +350,10 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
   // every other candidate starts from the unreachable value, far below any
   // reachable one within the library's input limits, so row 0 is a prefix
   // sum, taken 64 columns at a time across the lanes.
-  {
-    int64_t carry = 0;  // D(0, base - 1)
+  const int64_t neg = P.narrow ? (int64_t)pdp_neg<int32_t>() : pdp_neg<int64_t>();
+  if (wave == 0) {
+    int64_t* edge = edges + ebuf;  // buffer 1
+    int64_t carry = 0;             // D(0, base - 1)
     for (uint32_t base = 0; base <= n; base += 64) {
       const uint32_t j = base + lane;
       int64_t x = 0;
@@ -219,98 +365,30 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
       }
       const int64_t Dj = carry + x;
       if (j <= n) {
-        edge[3 * j] = j == 0 ? 0 : kNeg;
-        edge[3 * j + 1] = j == 0 ? kNeg : Dj;
-        edge[3 * j + 2] = kNeg;
+        const int64_t M0 = j == 0 ? 0 : neg, D0 = j == 0 ? neg : Dj;
+        edge[3 * j] = M0;
+        edge[3 * j + 1] = D0;
+        edge[3 * j + 2] = neg;
         dir[j] = (uint8_t)(j == 0 ? 0u : (1u | ((j == 1 ? 0u : 2u) << 2)));
+        if (m == 0 && j == n) {  // the cell (0, n) ends the alignment
+          s_fin[0] = M0;
+          s_fin[1] = D0;
+          s_fin[2] = neg;
+        }
       }
       carry = bcast64(Dj, 63);
     }
   }
   __threadfence_block();
   __syncthreads();
-  int64_t Mc = kNeg, Dc = kNeg, Ic = kNeg;
-  for (uint32_t i0 = 0; i0 < m; i0 += 64) {
-    const uint32_t i = i0 + 1 + lane;
-    const bool active = i <= m;
-    const bool terminal = i == m;  // gaps after the sequence's last residue
-    const int64_t* po = terminal ? dto : dgo;
-    const int64_t* pe = terminal ? dte : dge;
-    const uint32_t a = active ? A.seqs[P.seq + i - 1] : 0u;
-    const int32_t* crow = A.cost + P.cost + (uint64_t)a * n;
-    const bool writes_edge = lane == 63 && i0 + 64 < m;
-    uint8_t* dstrip = strips + (uint64_t)(i0 >> 6) * pdp_strip_bytes(n) + lane;
-    int64_t diag = kNeg;
-    Mc = Dc = Ic = kNeg;
-    // this lane's column values, loaded one step ahead: column j = t - lane
-    int64_t c_cost = 0, c_po = 0, c_pe = 0, c_if = 0, c_ie = 0, e_M = 0, e_D = 0, e_I = 0;
-    auto fetch = [&](int32_t jj) {
-      if (jj >= 1 && jj <= (int32_t)n) {
-        c_cost = crow[jj - 1];
-        c_po = po[jj - 1];
-        c_pe = pe[jj - 1];
-      }
-      if (jj >= 0 && jj <= (int32_t)n) {
-        c_if = ifirst[jj];
-        c_ie = iext[jj];
-        if (lane == 0) {
-          e_M = edge[3 * jj];
-          e_D = edge[3 * jj + 1];
-          e_I = edge[3 * jj + 2];
-        }
-      }
-    };
-    fetch(-(int32_t)lane);
-    for (uint32_t t = 0; t < n + 64; ++t) {
-      int64_t Mu = shr1_64(Mc), Du = shr1_64(Dc), Iu = shr1_64(Ic);
-      const int32_t j = (int32_t)t - (int32_t)lane;
-      if (lane == 0) {
-        Mu = e_M;
-        Du = e_D;
-        Iu = e_I;
-      }
-      const int64_t cost = c_cost, o = c_po, e = c_pe, f = c_if, x = c_ie;
-      fetch(j + 1);
-      if (active && j >= 0 && j <= (int32_t)n) {
-        int64_t M = kNeg, D = kNeg, I, b;
-        int ds = 0;
-        if (j >= 1) {
-          M = diag + cost;
-          ds = argmax3(Mc - o, Ic - o, Dc - e, &D);
-        }
-        const int is = argmax3(Mu - f, Du - f, Iu - x, &I);
-        const int bk = argmax3(M, D, I, &b);
-        dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
-        argmax3(Mu, Du, Iu, &diag);  // the cell above is the next column's diagonal
-        Mc = M;
-        Dc = D;
-        Ic = I;
-        if (writes_edge) {
-          edge[3 * j] = M;
-          edge[3 * j + 1] = D;
-          edge[3 * j + 2] = I;
-        }
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-  }
-  // the cell (m, n): held by the lane of row m, or row 0 when m = 0
-  int64_t fM, fD, fI;
-  if (m) {
-    const uint32_t src = (m - 1) & 63u;
-    fM = bcast64(Mc, src);
-    fD = bcast64(Dc, src);
-    fI = bcast64(Ic, src);
-  } else {
-    fM = edge[3 * n];
-    fD = edge[3 * n + 1];
-    fI = edge[3 * n + 2];
-  }
+  if (P.narrow) pdp_strips<int32_t>(P, A, nw, s_fin);
+  else pdp_strips<int64_t>(P, A, nw, s_fin);
+  const int64_t fM = s_fin[0], fD = s_fin[1], fI = s_fin[2];
   int64_t best;
   int st = argmax3(fM, fD, fI, &best);
-  // trace back; every lane walks the same path (uniform control flow), the
-  // choice bytes come through a 4 KB LDS window
+  // trace back; every lane of every remaining wave walks the same path
+  // (uniform control flow), the choice bytes come through a 4 KB LDS window
+  // that wave 0 fills; wave 0 writes the alignment
   uint8_t* ops = A.ops + P.ops;
   uint32_t i = m, j = n, k = 0;
   int win = -2;        // window's region: -1 row 0, s >= 0 strip s
@@ -328,7 +406,7 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
     } else if (i == 0) {
       break;
     }
-    if (lane == 0) ops[k] = (uint8_t)st;
+    if (threadIdx.x == 0) ops[k] = (uint8_t)st;
     ++k;
     const int region = ci == 0 ? -1 : (int)((ci - 1) >> 6);
     const uint64_t idx = ci == 0 ? cj : (uint64_t)(cj + ((ci - 1) & 63u)) * 64 + ((ci - 1) & 63u);
@@ -339,7 +417,7 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
       wlo = idx >= 4032 ? ((idx - 4032) & ~(uint64_t)63) : 0;
       __syncthreads();  // the previous window's reads are done
       const uint64_t off = wlo + (uint64_t)lane * 64;
-      if (off < size) {
+      if (wave == 0 && off < size) {
         const uint4* src = reinterpret_cast<const uint4*>(base + off);
 #pragma unroll
         for (int q = 0; q < 4; ++q) stage4[lane * 4 + q] = src[q];
@@ -363,12 +441,14 @@ __global__ __launch_bounds__(64) void pdp_dp_kernel(const PdpProb* __restrict__ 
   }
   __threadfence_block();
   __syncthreads();
-  for (uint32_t x = lane; x < k / 2; x += 64) {  // ops were written from the last column back
-    const uint8_t u = ops[x], v = ops[k - 1 - x];
-    ops[x] = v;
-    ops[k - 1 - x] = u;
+  if (wave == 0) {
+    for (uint32_t x = lane; x < k / 2; x += 64) {  // ops were written from the last column back
+      const uint8_t u = ops[x], v = ops[k - 1 - x];
+      ops[x] = v;
+      ops[k - 1 - x] = u;
+    }
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     A.score[blockIdx.x] = best;
     A.nops[blockIdx.x] = (i == 0 && j == 0) ? k : 0xFFFFFFFFu;  // all ones: the walk stopped early
   }
@@ -401,6 +481,9 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     if (gap_costs[c] > (int64_t)FAMSA_PROFILE_MAX_GAP || gap_costs[c] < -(int64_t)FAMSA_PROFILE_MAX_GAP)
       return set_error(FAMSA_LCS_EINVAL, "gap cost %lld outside [-%u, %u]", (long long)gap_costs[c],
                        FAMSA_PROFILE_MAX_GAP, FAMSA_PROFILE_MAX_GAP);
+  int64_t smax = 0, gmax = 0;  // largest score and gap cost magnitudes
+  for (uint32_t e = 0; e < sigma * sigma; ++e) smax = std::max<int64_t>(smax, subst[e] < 0 ? -(int64_t)subst[e] : subst[e]);
+  for (int c = 0; c < 4; ++c) gmax = std::max<int64_t>(gmax, gap_costs[c] < 0 ? -gap_costs[c] : gap_costs[c]);
   std::vector<PdpProb> pr(nprob);
   uint64_t o_seq = 0, o_rows = 0, o_cost = 0, o_col = 0, o_rowx = 0, o_edge = 0, o_dir = 0, o_ops = 0;
   uint32_t nmax = 0;
@@ -428,7 +511,9 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     d.m = (uint32_t)m;
     d.n = n;
     d.K = K;
-    d.pad = 0;
+    // every DP value is a sum of at most m + n + 1 terms of magnitude at most
+    // K max(|S|, |gap cost|); int32 when that stays below 2^28
+    d.narrow = ((uint64_t)m + n + 2) * (uint64_t)K * (uint64_t)std::max(smax, gmax) < (1ull << 28) ? 1u : 0u;
     d.seq = o_seq;
     d.rows = o_rows;
     d.cost = o_cost;
@@ -442,7 +527,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     o_cost += (uint64_t)sigma * n;
     o_col += (uint64_t)n + 1;
     o_rowx += K;
-    o_edge += 3 * ((uint64_t)n + 1);
+    o_edge += 6 * ((uint64_t)n + 1);  // two edge-row buffers
     o_dir += pdp_dir_bytes((uint32_t)m, n);
     o_ops += m + n;
     nmax = std::max(nmax, n);
@@ -503,7 +588,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
                      gap_costs[3]);
   FAMSA_HIP(hipGetLastError());
   FAMSA_HIP(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL(pdp_dp_kernel, dim3(nprob), dim3(64), 0, st, dprobs, A);
+  hipLaunchKernelGGL(pdp_dp_kernel, dim3(nprob), dim3(64 * kPdpWaves), 0, st, dprobs, A);
   FAMSA_HIP(hipGetLastError());
   FAMSA_HIP(hipEventRecord(ev[1], st));
   std::vector<uint8_t> hops(o_ops ? o_ops : 1);

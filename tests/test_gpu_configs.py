@@ -125,20 +125,23 @@ def test_c4_two_streams_with_graphs_equals_plain(c4_plain):
     assert got == plain
 
 
+@pytest.mark.timeout(900)
 def test_c5_jobs_sampled_in_the_serving_configuration():
-    # every job of the serving workload through the server as bench.py runs
-    # it (2^24-value, 2^41-cell steps, 256-row tiles), arrivals replayed at
-    # once; every tile of every job equals the job's tile when it runs alone
-    # (digests), seeded samples match the oracle and every value is within
-    # [0, min length]
+    # every job of the serving workload (all 200 jobs of the bench's mix)
+    # through the server as bench.py runs it (2^24-value, 2^41-cell steps,
+    # 256-row tiles), arrivals replayed at once; every tile of every job
+    # equals the job's tile when it runs alone (digests), seeded samples
+    # match the oracle and every value is within [0, min length]
+    import os
     from paper_1603_06958_amd import serve
-    jobs = inputs.c5(seed=4, njobs=40, rate_per_s=serve.C5_RATE_PER_S)  # the first 40 jobs of the bench's mix
+    jobs = inputs.c5(seed=4, njobs=200, rate_per_s=serve.C5_RATE_PER_S,
+                     workers=min(16, len(os.sched_getaffinity(0))))
     samplers = {}
     mixed = {}
 
     def on_tile(jid, t):
         if jid not in samplers:
-            samplers[jid] = Sampler(jobs[r_ids[jid]].batch, per_tile=30, seed=jid)
+            samplers[jid] = Sampler(jobs[r_ids[jid]].batch, per_tile=4, seed=jid)
         local = B.Tile.from_buffer_copy(t)  # the job's own batch holds one family
         local.family = 0
         mixed[(jid, int(t.row_begin), int(t.row_end))] = digest(B.tile_array(t))
@@ -164,7 +167,10 @@ def test_c5_jobs_sampled_in_the_serving_configuration():
         total += smp.check()
     assert total >= 1000
     # each job alone, through a plan with the same tile rows
-    for jid, i in r_ids.items():
-        alone = run_hashed(jobs[i].batch, tile_rows=serve.SERVE_TILE_ROWS)
+    for n, (jid, i) in enumerate(r_ids.items()):
+        alone = run_hashed(jobs[i].batch, tile_rows=serve.SERVE_TILE_ROWS, step_values=serve.SERVE_STEP_VALUES)
+        assert len(alone) == len([key for key in mixed if key[0] == jid])
         for (f, r0, r1), h in alone.items():
             assert mixed[(jid, r0, r1)] == h, (jid, r0)
+        if n % 50 == 49:
+            print(f"c5: {n + 1} jobs alone equal their tiles in the mix", flush=True)

@@ -86,3 +86,19 @@ def test_rejects_bad_input():
         B.profile_align([(p.seq, bad)], S, (1, 1, 1, 1))
     with pytest.raises(B.FamsaError):
         B.profile_align([(p.seq, np.zeros((0, 10), np.uint8))], S, (1, 1, 1, 1))
+
+
+def test_wide_values_and_mixed_batches():
+    # scores and gap costs near the library's limits: the DP runs in int64
+    # for these problems and in int32 for the small ones of the same batch
+    rng = np.random.default_rng(61)
+    S = (inputs.synthetic_subst(20, 6).astype(np.int64) * 85).astype(np.int32)  # |S| up to 1020
+    costs = (900_000, 30_000, 1_000_000, 50_000)
+    probs = [inputs.profile_problem(int(rng.integers(60, 200)), int(rng.integers(60, 200)), int(rng.integers(20, 60)),
+                                    rng) for _ in range(6)]
+    check_batch(probs, S, costs)
+    # one row and at most 40 columns and residues: below 2^28 even at these costs
+    small = [inputs.profile_problem(int(rng.integers(1, 40)), int(rng.integers(1, 40)), 1, rng) for _ in range(6)]
+    mixed = [p for pair in zip(probs, small) for p in pair]
+    check_batch(mixed, inputs.synthetic_subst(20, 6), (9, 2, 12, 3))
+    check_batch(mixed, S, costs)
