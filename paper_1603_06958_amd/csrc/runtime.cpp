@@ -145,26 +145,41 @@ int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq,
 }
 
 DeviceBatch DeviceBatchOwner::view() const {
-  return DeviceBatch{codes.as<uint8_t>(), dev_off.as<uint64_t>(), sym.as<uint8_t>(), sym_off.as<uint64_t>(),
-                     len.as<uint32_t>(),       mask_off.as<uint64_t>(), masks.as<uint32_t>(), values};
+  return DeviceBatch{codes, dev_off, sym, sym_off, len, mask_off, masks, values};
 }
 
 static inline uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+namespace {
+// Parts of a batch's device allocation, in bytes, from the code bytes (each
+// sequence padded to 32), the stream bytes and the mask dwords.
+struct BatchLayout {
+  uint64_t off[8], total;
+  BatchLayout(uint64_t cb, uint64_t sb, uint64_t mw, uint32_t n) {
+    const uint64_t sz[8] = {cb + 32, 8ull * (n + 1), 4ull * std::max<uint32_t>(n, 1), 8ull * (n + 1),
+                            8ull * (n + 1), std::max<uint64_t>(sb, 16), 8ull * (n + 1), mw * 4 + 16};
+    total = 0;
+    for (int i = 0; i < 8; ++i) {
+      off[i] = total;
+      total += round_up(sz[i], 256);
+    }
+  }
+};
+}  // namespace
+
 uint64_t DeviceBatchOwner::footprint(const uint64_t* seq_off, uint32_t nseq, uint32_t sigma) {
-  uint64_t cb = 0, words = 0;
+  uint64_t cb = 0, words = 0, sb = 0;
   for (uint32_t i = 0; i < nseq; ++i) {
     const uint64_t L = seq_off[i + 1] - seq_off[i];
     cb += round_up(L, kSeqAlign);
     words += (L + 31) / 32;
+    sb += ((L + 7) / 8 + 1) * 16;
   }
-  uint64_t sb = 0;
-  for (uint32_t i = 0; i < nseq; ++i) sb += ((seq_off[i + 1] - seq_off[i] + 7) / 8 + 1) * 16;
-  return cb + 32 + sb + (uint64_t)nseq * (8 + 8 + 4 + 8 + 8) + 16 + words * sigma * 4;
+  return BatchLayout(cb, sb, words * sigma, nseq).total;
 }
 
 int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uint32_t n, uint32_t sig,
-                             hipStream_t s) {
+                             hipStream_t s, bool wait) {
   nseq = n;
   sigma = sig;
   h_len.resize(n);
@@ -199,30 +214,47 @@ int DeviceBatchOwner::create(const uint8_t* hcodes, const uint64_t* seq_off, uin
     sb += ((uint64_t)(h_len[i] + 7) / 8 + 1) * 16;
   }
   h_sym_off[n] = sb;
-  std::vector<uint16_t> stream(sb / 2, 0);
+  std::vector<uint16_t> stream(std::max<uint64_t>(sb, 16) / 2, 0);
   for (uint32_t i = 0; i < n; ++i) {
     uint16_t* d = stream.data() + h_sym_off[i] / 2;
     const uint8_t* c = hcodes + seq_off[i];
     for (uint32_t t = 0; t < h_len[i]; ++t) d[t] = (uint16_t)(c[t] * 1024u);
   }
-  int rc;
-  if ((rc = upload(codes, packed, s))) return rc;
-  if ((rc = upload(dev_off, hoff, s))) return rc;
-  if ((rc = upload(len, h_len, s))) return rc;
-  if ((rc = upload(mask_off, hmo, s))) return rc;
-  if ((rc = upload(wprefix, hwp, s))) return rc;
-  if ((rc = upload(sym, stream, s))) return rc;
-  if ((rc = upload(sym_off, h_sym_off, s))) return rc;
-  if ((rc = masks.alloc(mw * 4 + 16))) return rc;
   h_dev_off = hoff;
   h_mask_off = hmo;
+  const BatchLayout lay(cb, sb, mw, n);
+  if (mem.bytes < lay.total) {
+    const int rc = mem.alloc(lay.total);
+    if (rc) return rc;
+  }
+  uint8_t* base = mem.as<uint8_t>();
+  codes = base + lay.off[0];
+  dev_off = reinterpret_cast<uint64_t*>(base + lay.off[1]);
+  len = reinterpret_cast<uint32_t*>(base + lay.off[2]);
+  mask_off = reinterpret_cast<uint64_t*>(base + lay.off[3]);
+  wprefix = reinterpret_cast<uint64_t*>(base + lay.off[4]);
+  sym = base + lay.off[5];
+  sym_off = reinterpret_cast<uint64_t*>(base + lay.off[6]);
+  masks = reinterpret_cast<uint32_t*>(base + lay.off[7]);
+  FAMSA_HIP(hipMemcpyAsync(codes, packed.data(), packed.size(), hipMemcpyHostToDevice, s));
+  FAMSA_HIP(hipMemcpyAsync(dev_off, h_dev_off.data(), 8ull * (n + 1), hipMemcpyHostToDevice, s));
+  if (n) FAMSA_HIP(hipMemcpyAsync(len, h_len.data(), 4ull * n, hipMemcpyHostToDevice, s));
+  FAMSA_HIP(hipMemcpyAsync(mask_off, h_mask_off.data(), 8ull * (n + 1), hipMemcpyHostToDevice, s));
+  FAMSA_HIP(hipMemcpyAsync(wprefix, hwp.data(), 8ull * (n + 1), hipMemcpyHostToDevice, s));
+  FAMSA_HIP(hipMemcpyAsync(sym, stream.data(), stream.size() * 2, hipMemcpyHostToDevice, s));
+  FAMSA_HIP(hipMemcpyAsync(sym_off, h_sym_off.data(), 8ull * (n + 1), hipMemcpyHostToDevice, s));
   const DeviceBatch v = view();
-  int e = launch_build_masks(v, wprefix.as<uint64_t>(), n, words, sigma, masks.as<uint32_t>(), s);
+  int e = launch_build_masks(v, wprefix, n, words, sigma, masks, s);
   if (e) return set_error(FAMSA_LCS_EDEVICE, "build_masks launch failed: %s", hipGetErrorString((hipError_t)e));
-  // host staging vectors above are freed on return: wait for the copies
-  FAMSA_HIP(hipStreamSynchronize(s));
-  bytes = codes.bytes + dev_off.bytes + len.bytes + mask_off.bytes + masks.bytes + wprefix.bytes + sym.bytes +
-          sym_off.bytes;
+  if (wait) {
+    // the host sources above are freed on return: wait for the copies
+    FAMSA_HIP(hipStreamSynchronize(s));
+  } else {
+    st_codes.swap(packed);
+    st_sym.swap(stream);
+    st_wprefix.swap(hwp);
+  }
+  bytes = mem.bytes;
   return 0;
 }
 

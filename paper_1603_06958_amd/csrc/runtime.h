@@ -27,6 +27,20 @@ struct DevMem {
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevMem() { reset(); }
   void reset();
   int alloc(size_t n);  // 0 or FAMSA_LCS_ENOMEM / EDEVICE (error text set)
@@ -72,20 +86,40 @@ int normalize_options(const famsa_lcs_options* in, Opts* out);
 int validate_batch(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, const uint32_t* fam_off,
                    uint32_t nfam, uint32_t sigma, std::vector<uint32_t>* fam_out, uint32_t* max_len);
 
-// A batch resident on the device with its masks.
+// A batch resident on the device with its masks, in one device allocation
+// (codes, offsets, lengths, column streams and masks at 256-byte aligned
+// offsets), so a serving job costs one allocation and its memory can be
+// handed to the next job instead of freed.
 struct DeviceBatchOwner {
-  DevMem codes, dev_off, len, mask_off, masks, wprefix, sym, sym_off;
+  DevMem mem;
+  uint8_t* codes = nullptr;      // 32-byte aligned, zero-padded sequences
+  uint64_t* dev_off = nullptr;
+  uint32_t* len = nullptr;
+  uint64_t* mask_off = nullptr;
+  uint64_t* wprefix = nullptr;   // prefix sums of mask dwords per sequence
+  uint8_t* sym = nullptr;        // column streams
+  uint64_t* sym_off = nullptr;
+  uint32_t* masks = nullptr;
   std::vector<uint32_t> h_len;       // per sequence
   std::vector<uint64_t> h_lenprefix; // prefix sums of lengths (nseq + 1)
   std::vector<uint64_t> h_dev_off;   // device byte offset of each sequence in `codes`
   std::vector<uint64_t> h_mask_off;  // dword offset of each sequence's masks in `masks`
   std::vector<uint64_t> h_sym_off;   // byte offset of each sequence's column stream in `sym`
+  // host sources of the uploads, kept while they may be in flight (create with wait = false)
+  std::vector<uint8_t> st_codes;
+  std::vector<uint16_t> st_sym;
+  std::vector<uint64_t> st_wprefix;
   uint32_t nseq = 0, max_len = 0, sigma = 0;
   uint32_t values = FAMSA_LCS_VALUES_LCS;  // tile contents, from the plan's flags
-  uint64_t bytes = 0;
+  uint64_t bytes = 0;                      // device bytes held (mem's size)
   DeviceBatch view() const;
-  // Copies the batch (validated) to the device and builds the masks on `s`.
-  int create(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, uint32_t sigma, hipStream_t s);
+  // Copies the batch (validated) to the device and builds the masks on `s`,
+  // reusing `mem` when it is already large enough.  With wait = false the call
+  // does not synchronise: the host sources stay in this object, and work
+  // ordered on `s` after the call sees the batch.
+  int create(const uint8_t* codes, const uint64_t* seq_off, uint32_t nseq, uint32_t sigma, hipStream_t s,
+             bool wait = true);
+  // Device bytes create() needs for this batch.
   static uint64_t footprint(const uint64_t* seq_off, uint32_t nseq, uint32_t sigma);
 };
 

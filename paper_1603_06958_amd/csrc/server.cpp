@@ -91,6 +91,10 @@ struct famsa_lcs_server_s {
   uint64_t step_cells = 0;  // 0: steps bounded by values only
   std::map<uint32_t, std::unique_ptr<Job>> jobs;
   std::deque<Job*> queue;
+  // device memory of finished jobs, kept for later jobs: freeing device
+  // memory waits for the whole device, which would stall the step pipeline
+  std::vector<DevMem> spare;
+  uint64_t spare_bytes = 0;
   std::vector<Job*> active;
   uint32_t next_id = 0;
   hipStream_t cs = nullptr, xs = nullptr;  // the device's shared compute and copy streams
@@ -122,16 +126,34 @@ struct famsa_lcs_server_s {
 int famsa_lcs_server_s::admit() {
   for (auto it = queue.begin(); it != queue.end();) {
     Job* j = *it;
-    if (in_use + j->footprint > budget - fixed) {
+    // the smallest spare block that holds the job, if any (no more than twice its size)
+    int reuse = -1;
+    for (size_t b = 0; b < spare.size(); ++b)
+      if (spare[b].bytes >= j->footprint && spare[b].bytes <= 2 * j->footprint + (1u << 20) &&
+          (reuse < 0 || spare[b].bytes < spare[reuse].bytes))
+        reuse = (int)b;
+    const uint64_t need = reuse >= 0 ? 0 : j->footprint;
+    while (reuse < 0 && !spare.empty() && in_use + spare_bytes + need > budget - fixed) {
+      spare_bytes -= spare.back().bytes;  // make room: this free waits for the device
+      spare.pop_back();
+    }
+    if (in_use + spare_bytes + need > budget - fixed) {
       if (queue.front()->bypassed >= kMaxBypass) break;
       ++it;
       continue;
     }
     j->dev.reset(new DeviceBatchOwner());
-    int rc = j->dev->create(j->codes.data(), j->off.data(), j->k, opt.sigma, cs);
+    if (reuse >= 0) {
+      spare_bytes -= spare[reuse].bytes;
+      std::swap(j->dev->mem.p, spare[reuse].p);
+      std::swap(j->dev->mem.bytes, spare[reuse].bytes);
+      spare.erase(spare.begin() + reuse);
+    }
+    // no wait: the uploads and mask build are ordered on cs before the job's first step
+    int rc = j->dev->create(j->codes.data(), j->off.data(), j->k, opt.sigma, cs, false);
     if (rc) return rc;
     in_use += j->dev->bytes;
-    peak = std::max(peak, in_use + fixed);
+    peak = std::max(peak, in_use + spare_bytes + fixed);
     j->state = 1;
     std::vector<uint8_t>().swap(j->codes);
     active.push_back(j);
@@ -186,8 +208,8 @@ int famsa_lcs_server_s::compose(Slot& sl, Staging& st) {
     sf.fam = FamilyRef{(uint32_t)st.len.size(), j->k};
     sf.whole = j->whole;
     const DeviceBatchOwner& d = *j->dev;
-    const uint64_t cbase = (uint64_t)(uintptr_t)d.codes.p, mbase = (uint64_t)(uintptr_t)d.masks.p / 4;
-    const uint64_t sbase = (uint64_t)(uintptr_t)d.sym.p;
+    const uint64_t cbase = (uint64_t)(uintptr_t)d.codes, mbase = (uint64_t)(uintptr_t)d.masks / 4;
+    const uint64_t sbase = (uint64_t)(uintptr_t)d.sym;
     for (uint32_t i = 0; i < j->k; ++i) {
       st.devoff.push_back(cbase + d.h_dev_off[i]);
       st.symoff.push_back(sbase + d.h_sym_off[i]);
@@ -280,6 +302,12 @@ int famsa_lcs_server_s::deliver(int si, famsa_lcs_tile_fn fn, void* user) {
     if (j->delivered == j->tiles.size()) {
       j->state = 2;
       in_use -= j->dev->bytes;
+      // keep the job's device memory for a later job; the step that read it has
+      // completed (its copy event was waited on above), and later steps do not
+      spare.emplace_back();
+      std::swap(spare.back().p, j->dev->mem.p);
+      std::swap(spare.back().bytes, j->dev->mem.bytes);
+      spare_bytes += spare.back().bytes;
       j->dev.reset();
       active.erase(std::find(active.begin(), active.end(), j));
     }
@@ -414,7 +442,7 @@ int famsa_lcs_server_job_state(const famsa_lcs_server_t* s, uint32_t id, int* st
 int famsa_lcs_server_memory(const famsa_lcs_server_t* s, uint64_t* in_use, uint64_t* peak) {
   clear_error();
   if (!s) return set_error(FAMSA_LCS_EINVAL, "server is NULL");
-  if (in_use) *in_use = s->in_use + s->fixed;
+  if (in_use) *in_use = s->in_use + s->spare_bytes + s->fixed;
   if (peak) *peak = s->peak;
   return 0;
 }
