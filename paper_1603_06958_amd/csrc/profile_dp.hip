@@ -11,14 +11,13 @@
 //   pdp_cols_kernel -- a thread per column j: the profile's per-column
 //                      symbol counters (LDS histogram over the rows), the
 //                      column-to-symbol cost table cost[a][j] = sum_x
-//                      count[j][x] S[x][a], w_j = residues in column j and
-//                      the four gap costs of a gap in the sequence against
-//                      column j (w_j times To, Te, Go, Ge); a thread per
-//                      boundary p: the cost of the first and of each further
-//                      gap column inserted into the profile there, from the
-//                      counts of rows in each of the four situations
-//                      (terminal or inside, next to a gap or opening one);
-//   pdp_dp_kernel   -- a workgroup of up to four waves per problem: the
+//                      count[j][x] S[x][a] and w_j = residues in column j; a
+//                      thread per boundary p: the cost of the first and of
+//                      each further gap column inserted into the profile
+//                      there, from the counts of rows in each of the four
+//                      situations (terminal or inside, next to a gap or
+//                      opening one);
+//   pdp_dp_kernel   -- a workgroup of up to sixteen waves per problem: the
 //                      three-state DP
 //                        M(i,j) = best(i-1,j-1) + cost[a_i][j]
 //                        D(i,j) = max(M - o w_j, I - o w_j, D - e w_j)(i,j-1)
@@ -26,16 +25,18 @@
 //                      over strips of 64 rows (a lane per row), each strip
 //                      swept along anti-diagonals: at step t lane l does
 //                      column t - l, takes the cell above from lane l - 1
-//                      (and lane 0 from the strip above's last row, kept in
-//                      global memory), and records the three choices of each
-//                      cell in one byte; consecutive strips run on different
-//                      waves, each a fixed number of steps behind the strip
-//                      above, in phases separated by barriers; then the
-//                      alignment is traced back from (m, n), staging 64 steps
-//                      of choices in LDS at a time.
-// Ties take the first maximum in the order written (M, D, I), as a fixed
-// rule, so the alignment and not only its score is unique.  All DP
-// arithmetic is int64.
+//                      (and lane 0 from the strip above's last row, an edge
+//                      row), and records the three choices of each cell in
+//                      one byte; consecutive strips run on different waves,
+//                      each a fixed number of steps behind the strip above,
+//                      in phases separated by barriers; then the alignment is
+//                      traced back from (m, n), staging the choices in LDS
+//                      4 KB at a time.
+// The DP reads the per-column records, the cost table and the edge rows from
+// LDS when the problem's share fits (it is copied in first), else from
+// global memory.  Ties take the first maximum in the order written (M, D, I),
+// as a fixed rule, so the alignment and not only its score is unique.  The
+// DP runs in int32 when every value fits 28 bits, else in int64.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -43,6 +44,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <numeric>
 #include <vector>
 
 #include "runtime.h"
@@ -56,31 +58,42 @@ double g_profile_dp_ms = 0;  // duration of the last batch's DP launch
 struct PdpProb {        // one problem's offsets into the batch arrays
   uint64_t seq;         // seqs (bytes)
   uint64_t rows;        // rows (bytes), K rows of n
-  uint64_t cost;        // cost (int32), sigma x n
-  uint64_t col;         // w (int32, n); dgap (int64, 4 n); ifirst, iext (int64, n + 1)
+  uint64_t cost;        // cost (int32), sigma x max(n, 1)
+  uint64_t col;         // rec (records, n + 1)
   uint64_t rowx;        // first, last (int32, K)
-  uint64_t edge;        // edge (int64, 2 buffers of 3 (n + 1))
+  uint64_t edge;        // edge (records, 2 buffers of n + 1)
   uint64_t dir;         // dir (bytes): row 0, then strips of (n + 64) x 64
   uint64_t ops;         // ops (bytes), m + n
   uint32_t m, n, K;
   uint32_t narrow;      // 1: every DP value fits 28 bits, so the DP runs in int32
+  uint32_t idx;         // the problem's place in the caller's batch (launch order is largest first)
+  uint32_t lds;         // 1: the DP reads its records, costs and edge rows from LDS
+  uint32_t cost16;      // 1: every cost fits int16 (K max|S| < 2^15), so LDS holds them as int16
+  uint32_t pad;
+};
+
+// Four values of one column or boundary.  Column record j (0..n):
+// w_j (residues in column j, 1-based; 0 for j = 0), f_j and x_j (the costs
+// of a first and a further gap column inserted at boundary j), 0.  Edge
+// record j: M, D, I of the strip's last row at column j.
+template <typename E>
+struct alignas(4 * sizeof(E)) PdpRec {
+  E v[4];
 };
 
 struct PdpArrays {
   const uint8_t* seqs;
   const uint8_t* rows;
   int32_t* cost;
-  int32_t* w;
-  int64_t* dgap;    // [4][n] per problem: w_j To, w_j Te, w_j Go, w_j Ge
-  int64_t* ifirst;
-  int64_t* iext;
+  PdpRec<int64_t>* rec;
   int32_t* first;
   int32_t* last;
-  int64_t* edge;
+  PdpRec<int64_t>* edge;
   uint8_t* dir;
   uint8_t* ops;
   int64_t* score;
   uint32_t* nops;
+  int64_t To, Te, Go, Ge;  // gap costs: terminal open / extend, inside open / extend
 };
 
 template <typename T>
@@ -118,8 +131,7 @@ __global__ __launch_bounds__(256) void pdp_rows_kernel(const PdpProb* __restrict
 
 // blockIdx.y picks 256 columns (boundaries) of problem blockIdx.x.
 __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict__ probs, PdpArrays A,
-                                                       const int32_t* __restrict__ subst, uint32_t sigma, int64_t To,
-                                                       int64_t Te, int64_t Go, int64_t Ge) {
+                                                       const int32_t* __restrict__ subst, uint32_t sigma) {
   __shared__ uint32_t hist[FAMSA_LCS_MAX_ALPHABET][256];
   __shared__ int32_t S[FAMSA_LCS_MAX_ALPHABET * FAMSA_LCS_MAX_ALPHABET];
   const PdpProb P = probs[blockIdx.x];
@@ -144,17 +156,15 @@ __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict
     if (inside) { if (adj) ++cIA; else ++cIO; }
     else { if (adj) ++cTA; else ++cTO; }
   }
-  A.ifirst[P.col + j] = (int64_t)cTA * Te + (int64_t)cTO * To + (int64_t)cIA * Ge + (int64_t)cIO * Go;
-  A.iext[P.col + j] = (int64_t)(cTA + cTO) * Te + (int64_t)(cIA + cIO) * Ge;
+  PdpRec<int64_t>* rec = A.rec + P.col;
+  rec[j].v[1] = (int64_t)cTA * A.Te + (int64_t)cTO * A.To + (int64_t)cIA * A.Ge + (int64_t)cIO * A.Go;
+  rec[j].v[2] = (int64_t)(cTA + cTO) * A.Te + (int64_t)(cIA + cIO) * A.Ge;
+  rec[j].v[3] = 0;
+  if (j == 0) rec[0].v[0] = 0;
   if (j == P.n) return;
   int32_t wj = 0;
   for (uint32_t x = 0; x < sigma; ++x) wj += (int32_t)hist[x][tid];
-  A.w[P.col + j] = wj;
-  int64_t* dg = A.dgap + 4 * P.col;
-  dg[j] = (int64_t)wj * To;
-  dg[P.n + j] = (int64_t)wj * Te;
-  dg[2 * P.n + j] = (int64_t)wj * Go;
-  dg[3 * P.n + j] = (int64_t)wj * Ge;
+  rec[j + 1].v[0] = wj;  // 1-based column j + 1
   for (uint32_t a = 0; a < sigma; ++a) {
     int32_t c = 0;
     for (uint32_t x = 0; x < sigma; ++x) c += (int32_t)hist[x][tid] * S[x * sigma + a];
@@ -162,14 +172,16 @@ __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict
   }
 }
 
-// Lane l receives lane l - 1's value (DPP wave shift; lane 0 keeps its own).
-__device__ __forceinline__ int32_t shr1(int32_t v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+// Lane l receives lane l - 1's value and lane 0 receives `in` (DPP wave
+// shift right by one: the lane without a source keeps the old value).
+__device__ __forceinline__ int32_t shr1(int32_t v, int32_t in) {
+  return __builtin_amdgcn_update_dpp(in, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
-__device__ __forceinline__ int64_t shr1(int64_t v) {
+__device__ __forceinline__ int64_t shr1(int64_t v, int64_t in) {
   const int lo = (int)(uint32_t)(uint64_t)v, hi = (int)(uint32_t)((uint64_t)v >> 32);
-  const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
-  const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
+  const int ilo = (int)(uint32_t)(uint64_t)in, ihi = (int)(uint32_t)((uint64_t)in >> 32);
+  const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(ilo, lo, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(ihi, hi, 0x138, 0xF, 0xF, false);
   return (int64_t)(((uint64_t)b << 32) | a);
 }
 
@@ -178,6 +190,11 @@ __device__ __forceinline__ int64_t shfl_up64(int64_t v, int d) {
   const int32_t hi = __shfl_up((int32_t)(uint32_t)((uint64_t)v >> 32), d, 64);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
+
+// Products of a residue count (< 2^21) and a gap cost (|c| <= 2^20): the
+// 24-bit multiply is exact for them and full rate in int32.
+__device__ __forceinline__ int32_t wmul(int32_t w, int32_t c) { return __mul24(w, c); }
+__device__ __forceinline__ int64_t wmul(int64_t w, int64_t c) { return w * c; }
 
 // Region of a problem's choice bytes: row 0 (rounded up to 64 bytes), then
 // per strip of 64 rows (n + 64) steps x 64 lanes.  Cell (i, j), i >= 1, is
@@ -194,15 +211,28 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, uint32_t src) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Several waves per problem.  Strip s (rows 64 s + 1 .. 64 s + 64) runs its
-// sweep steps [q C, (q + 1) C) in phase 2 s + q on wave s mod nw.  Lane 0 of
-// strip s reads, at step t, the edge value lane 63 of strip s - 1 wrote at
-// its step t + 63, which the two-phase lag with C >= 64 makes an earlier
-// phase; C >= (n + 64) / (2 nw) keeps a wave's strips apart in time.  Phases
-// end at a barrier.  Strip s reads edge buffer (s + 1) mod 2 and writes
-// buffer s mod 2 (row 0 is buffer 1): strip s + 2 overwrites a column of
-// buffer s mod 2 two phases after strip s + 1 has read it.
-constexpr uint32_t kPdpWaves = 4;
+// Phases.  A problem's sweep of n + 64 steps per strip is cut into Q chunks
+// of kPdpChunk steps; strip s runs chunk q in phase start(s) + q on wave
+// s mod nw, and every phase ends at a barrier.  Lane 0 of strip s + 1 reads
+// the edge record of column t one step before its step t; lane 63 of strip
+// s writes it at its step t + 63, at most 64 / kPdpChunk phases later in the
+// strip's own chunks, so strips kPdpLag = 1 + 64 / kPdpChunk phases apart
+// always find it written in an earlier phase.  A wave's strips are
+// Period = max(Q, nw kPdpLag) phases apart:
+//   start(s) = (s mod nw) kPdpLag + (s / nw) Period,
+// which keeps consecutive strips at least kPdpLag phases apart and a wave's
+// strips from overlapping.  Strip s writes edge buffer s mod 2 and reads
+// buffer (s + 1) mod 2 (row 0 is buffer 1): strip s + 2 rewrites a column of
+// buffer s mod 2 in a later phase than the one in which strip s + 1 read it.
+constexpr uint32_t kPdpWaves = 16;
+constexpr uint32_t kPdpChunk = 16;
+constexpr uint32_t kPdpLag = 1 + (64 + kPdpChunk - 1) / kPdpChunk;
+
+__host__ __device__ inline uint32_t pdp_waves(uint32_t m, uint32_t n) {
+  const uint32_t S = (m + 63) / 64, Q = (n + 64 + kPdpChunk - 1) / kPdpChunk;
+  const uint32_t want = (Q + kPdpLag - 1) / kPdpLag;  // more waves than this would wait for their strips
+  return std::max(1u, std::min(kPdpWaves, std::min(S, want)));
+}
 
 // The unreachable value of each value type: far enough below every reachable
 // value (|value| < 2^28 for int32, < 2^58 for int64 within the input limits)
@@ -214,104 +244,160 @@ __host__ __device__ constexpr int32_t pdp_neg<int32_t>() { return INT32_MIN / 4;
 template <>
 __host__ __device__ constexpr int64_t pdp_neg<int64_t>() { return INT64_MIN / 4; }
 
-// The strips of one problem in value type T (int32 when every value fits
-// 28 bits, else int64); phases as described above.  Edge rows and the final
-// cell are kept as int64 holding T values.
-template <typename T>
-__device__ __forceinline__ void pdp_strips(const PdpProb& P, const PdpArrays& A, uint32_t nw, int64_t* s_fin) {
+// One problem's DP inputs as the strips read them: in LDS (E = T, costs
+// int32 or int16) or in global memory (E = int64, costs int32).
+template <typename E, typename C>
+struct PdpView {
+  const PdpRec<E>* rec;  // n + 1 column records
+  const C* cost;         // sigma rows of max(n, 1)
+  PdpRec<E>* edge;       // two buffers of n + 1
+};
+
+// LDS bytes a problem needs for its records, costs and edge rows.
+__host__ __device__ inline uint64_t pdp_lds_bytes(uint32_t n, uint32_t sigma, uint32_t value_bytes,
+                                                  uint32_t cost_bytes) {
+  return 16ull * value_bytes / 4 * 3ull * (n + 1) + (uint64_t)cost_bytes * sigma * std::max(n, 1u);
+}
+
+// Row 0 (wave 0): gaps in the sequence before its first residue (terminal
+// costs).  M(0,0) = 0 and D(0,1) comes from it; D(0,j), j >= 2, extends
+// D(0,j-1); every other candidate starts from the unreachable value, far
+// below any reachable one within the library's input limits, so row 0 is a
+// prefix sum, taken 64 columns at a time across the lanes.  Written to edge
+// buffer 1.
+template <typename T, typename E, typename C>
+__device__ void pdp_row0(const PdpProb& P, const PdpArrays& A, const PdpView<E, C>& V, uint8_t* dir,
+                         int64_t* s_fin) {
+  const uint32_t lane = threadIdx.x & 63u, n = P.n;
+  constexpr T neg = pdp_neg<T>();
+  PdpRec<E>* edge = V.edge + (n + 1);
+  int64_t carry = 0;  // D(0, base - 1)
+  for (uint32_t base = 0; base <= n; base += 64) {
+    const uint32_t j = base + lane;
+    int64_t x = 0;
+    if (j >= 1 && j <= n) x = -(int64_t)V.rec[j].v[0] * (j == 1 ? A.To : A.Te);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t y = shfl_up64(x, d);
+      if ((int)lane >= d) x += y;
+    }
+    const int64_t Dj = carry + x;
+    if (j <= n) {
+      const int64_t M0 = j == 0 ? 0 : (int64_t)neg, D0 = j == 0 ? (int64_t)neg : Dj;
+      PdpRec<E> r;
+      r.v[0] = (E)M0;
+      r.v[1] = (E)D0;
+      r.v[2] = (E)neg;
+      r.v[3] = 0;
+      edge[j] = r;
+      dir[j] = (uint8_t)(j == 0 ? 0u : (1u | ((j == 1 ? 0u : 2u) << 2)));
+      if (P.m == 0 && j == n) {  // the cell (0, n) ends the alignment
+        s_fin[0] = M0;
+        s_fin[1] = D0;
+        s_fin[2] = (int64_t)neg;
+      }
+    }
+    carry = bcast64(Dj, 63);
+  }
+}
+
+// The strips of one problem in value type T; phases as described above.
+template <typename T, typename E, typename C>
+__device__ void pdp_strips(const PdpProb& P, const PdpArrays& A, const PdpView<E, C>& V, uint32_t nw,
+                           int64_t* s_fin) {
   constexpr T neg = pdp_neg<T>();
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, m = P.m, n = P.n;
   const uint32_t S = (m + 63u) >> 6;
-  const int64_t* dto = A.dgap + 4 * P.col;
-  const int64_t* dte = dto + n;
-  const int64_t* dgo = dto + 2 * n;
-  const int64_t* dge = dto + 3 * n;
-  const int64_t* ifirst = A.ifirst + P.col;
-  const int64_t* iext = A.iext + P.col;
-  int64_t* edges = A.edge + P.edge;
-  const uint64_t ebuf = 3ull * (n + 1);
+  const int32_t nm1 = (int32_t)std::max(n, 1u) - 1;
   uint8_t* strips = A.dir + P.dir + pdp_row0_bytes(n);
   const uint32_t steps = n + 64;
-  const uint32_t C = max(64u, (steps + 2 * nw - 1) / (2 * nw));
-  const uint32_t Q = (steps + C - 1) / C;
-  const uint32_t nphase = S ? 2 * (S - 1) + Q : 0;
+  const uint32_t Q = (steps + kPdpChunk - 1) / kPdpChunk;
+  const uint32_t period = std::max(Q, nw * kPdpLag);
+  const uint32_t last = S ? ((S - 1) % nw) * kPdpLag + ((S - 1) / nw) * period : 0;
+  const uint32_t nphase = S ? last + Q : 0;
+  const uint32_t w0 = wave * kPdpLag;  // this wave's first phase
   // this wave's current strip
-  T Mc = neg, Dc = neg, Ic = neg, diag = neg;
-  T c_cost = 0, c_po = 0, c_pe = 0, c_if = 0, c_ie = 0, e_M = 0, e_D = 0, e_I = 0;
+  T Mc = neg, Dc = neg, Ic = neg, diag = neg, Oc = 0, Ec = 0;
   bool active = false, writes_edge = false;
-  const int64_t* po = dgo;
-  const int64_t* pe = dge;
-  const int32_t* crow = A.cost + P.cost;
-  const int64_t* ein = edges;
-  int64_t* eout = edges;
+  const C* crow = V.cost;
+  const PdpRec<E>* ein = V.edge;
+  PdpRec<E>* eout = V.edge;
   uint8_t* dstrip = strips;
-  auto fetch = [&](int32_t jj) {
-    if (jj >= 1 && jj <= (int32_t)n) {
-      c_cost = (T)crow[jj - 1];
-      c_po = (T)po[jj - 1];
-      c_pe = (T)pe[jj - 1];
-    }
-    if (jj >= 0 && jj <= (int32_t)n) {
-      c_if = (T)ifirst[jj];
-      c_ie = (T)iext[jj];
-      if (lane == 0) {
-        e_M = (T)ein[3 * jj];
-        e_D = (T)ein[3 * jj + 1];
-        e_I = (T)ein[3 * jj + 2];
+  // what one step reads: this lane's cost, w, f and x at its column and the
+  // edge record lane 0 needs
+  struct Col {
+    T cost, w, f, x, eM, eD, eI;
+  };
+  // the values at column jj (clamped: a lane outside the matrix reads a valid
+  // record and never uses it) and the edge record at column je
+  auto fetch = [&](int32_t jj, int32_t je) {
+    const int32_t jc = min(max(jj, 0), (int32_t)n), jm = min(max(jj - 1, 0), nm1);
+    const PdpRec<E> r = V.rec[jc];
+    const PdpRec<E> x = ein[min(max(je, 0), (int32_t)n)];
+    return Col{(T)crow[jm], (T)r.v[0], (T)r.v[1], (T)r.v[2], (T)x.v[0], (T)x.v[1], (T)x.v[2]};
+  };
+  auto step = [&](uint32_t t, const Col& c) {
+    const T Mu = shr1(Mc, c.eM), Du = shr1(Dc, c.eD), Iu = shr1(Ic, c.eI);
+    const int32_t j = (int32_t)t - (int32_t)lane;
+    if (active && j >= 0 && j <= (int32_t)n) {
+      const T o = wmul(c.w, Oc), e = wmul(c.w, Ec);
+      T M = neg, D = neg, I, b;
+      int ds = 0;
+      if (j >= 1) {
+        M = diag + c.cost;
+        ds = argmax3(Mc - o, Ic - o, Dc - e, &D);
+      }
+      const int is = argmax3(Mu - c.f, Du - c.f, Iu - c.x, &I);
+      const int bk = argmax3(M, D, I, &b);
+      dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
+      diag = max(max(Mu, Du), Iu);  // the cell above is the next column's diagonal
+      Mc = M;
+      Dc = D;
+      Ic = I;
+      if (writes_edge) {
+        PdpRec<E> rr;
+        rr.v[0] = (E)M;
+        rr.v[1] = (E)D;
+        rr.v[2] = (E)I;
+        rr.v[3] = 0;
+        eout[j] = rr;
       }
     }
   };
+  Col cur{};  // the next step's values, loaded one step ahead
   for (uint32_t p = 0; p < nphase; ++p) {
-    if (p >= 2 * wave) {
-      const uint32_t s = wave + nw * ((p / 2 - wave) / nw);  // latest strip of this wave started by phase p
-      if (s < S && p < 2 * s + Q) {
-        const uint32_t q = p - 2 * s;
+    if (p >= w0) {
+      const uint32_t r = (p - w0) / period, q = p - w0 - r * period, s = wave + r * nw;
+      if (s < S && q < Q) {
         if (q == 0) {  // a new strip
           const uint32_t i = 64 * s + 1 + lane;
           active = i <= m;
           const bool terminal = i == m;  // gaps after the sequence's last residue
-          po = terminal ? dto : dgo;
-          pe = terminal ? dte : dge;
+          Oc = (T)(terminal ? A.To : A.Go);
+          Ec = (T)(terminal ? A.Te : A.Ge);
           const uint32_t a = active ? A.seqs[P.seq + i - 1] : 0u;
-          crow = A.cost + P.cost + (uint64_t)a * n;
+          crow = V.cost + (uint64_t)a * (nm1 + 1);
           writes_edge = lane == 63 && s + 1 < S;
-          ein = edges + ((s + 1) & 1u) * ebuf;
-          eout = edges + (s & 1u) * ebuf;
+          ein = V.edge + ((s + 1) & 1u) * (n + 1);
+          eout = V.edge + (s & 1u) * (n + 1);
           dstrip = strips + (uint64_t)s * pdp_strip_bytes(n) + lane;
           Mc = Dc = Ic = diag = neg;
-          fetch(-(int32_t)lane);
+          cur = fetch(-(int32_t)lane, 0);
         }
-        const uint32_t t1 = min((q + 1) * C, steps);
-        for (uint32_t t = q * C; t < t1; ++t) {
-          T Mu = shr1(Mc), Du = shr1(Dc), Iu = shr1(Ic);
-          const int32_t j = (int32_t)t - (int32_t)lane;
-          if (lane == 0) {
-            Mu = e_M;
-            Du = e_D;
-            Iu = e_I;
-          }
-          const T cost = c_cost, o = c_po, e = c_pe, f = c_if, x = c_ie;
-          fetch(j + 1);
-          if (active && j >= 0 && j <= (int32_t)n) {
-            T M = neg, D = neg, I, b;
-            int ds = 0;
-            if (j >= 1) {
-              M = diag + cost;
-              ds = argmax3(Mc - o, Ic - o, Dc - e, &D);
-            }
-            const int is = argmax3(Mu - f, Du - f, Iu - x, &I);
-            const int bk = argmax3(M, D, I, &b);
-            dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
-            argmax3(Mu, Du, Iu, &diag);  // the cell above is the next column's diagonal
-            Mc = M;
-            Dc = D;
-            Ic = I;
-            if (writes_edge) {
-              eout[3 * j] = (int64_t)M;
-              eout[3 * j + 1] = (int64_t)D;
-              eout[3 * j + 2] = (int64_t)I;
-            }
-          }
+        const uint32_t t1 = min((q + 1) * kPdpChunk, steps);
+        uint32_t t = q * kPdpChunk;
+        // two steps per iteration, the loads alternating between two sets of
+        // registers, so that no step waits for the load it has just issued
+        for (; t + 1 < t1; t += 2) {
+          const Col nx = fetch((int32_t)(t + 1) - (int32_t)lane, (int32_t)t + 1);
+          step(t, cur);
+          cur = fetch((int32_t)(t + 2) - (int32_t)lane, (int32_t)t + 2);
+          step(t + 1, nx);
+        }
+        if (t < t1) {
+          const Col nx = fetch((int32_t)(t + 1) - (int32_t)lane, (int32_t)t + 1);
+          step(t, cur);
+          cur = nx;
         }
         if (s + 1 == S && t1 == steps && lane == ((m - 1) & 63u)) {  // the cell (m, n)
           s_fin[0] = (int64_t)Mc;
@@ -325,70 +411,79 @@ __device__ __forceinline__ void pdp_strips(const PdpProb& P, const PdpArrays& A,
   }
 }
 
+template <typename T, typename E, typename C>
+__device__ void pdp_dp(const PdpProb& P, const PdpArrays& A, const PdpView<E, C>& V, uint8_t* dir, uint32_t nw,
+                       int64_t* s_fin) {
+  if ((threadIdx.x >> 6) == 0) pdp_row0<T, E, C>(P, A, V, dir, s_fin);
+  __threadfence_block();
+  __syncthreads();
+  pdp_strips<T, E, C>(P, A, V, nw, s_fin);
+}
 
-__global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* __restrict__ probs, PdpArrays A) {
+// Copy one problem's records (as T) and cost table into LDS; edge rows are
+// written there by the DP itself.
+template <typename T, typename C>
+__device__ PdpView<T, C> pdp_stage(const PdpProb& P, const PdpArrays& A, char* lds, uint32_t sigma) {
+  const uint32_t n = P.n, n1 = std::max(n, 1u);
+  PdpRec<T>* rec = reinterpret_cast<PdpRec<T>*>(lds);
+  PdpRec<T>* edge = rec + (n + 1);
+  C* cost = reinterpret_cast<C*>(edge + 2 * (n + 1));
+  const PdpRec<int64_t>* g = A.rec + P.col;
+  for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) {
+    const PdpRec<int64_t> x = g[j];
+    PdpRec<T> y;
+    y.v[0] = (T)x.v[0];
+    y.v[1] = (T)x.v[1];
+    y.v[2] = (T)x.v[2];
+    y.v[3] = 0;
+    rec[j] = y;
+  }
+  const int32_t* gc = A.cost + P.cost;
+  for (uint32_t e = threadIdx.x; e < sigma * n1; e += blockDim.x) cost[e] = (C)gc[e];
+  return PdpView<T, C>{rec, cost, edge};
+}
+
+__global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* __restrict__ probs, PdpArrays A,
+                                                                 uint32_t sigma) {
+  extern __shared__ uint4 pdp_lds4[];
   __shared__ uint4 stage4[256];  // 4 KB window of choice bytes
   __shared__ int64_t s_fin[3];
+  char* lds = reinterpret_cast<char*>(pdp_lds4);
   const uint8_t* stage = reinterpret_cast<const uint8_t*>(stage4);
   const PdpProb P = probs[blockIdx.x];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, m = P.m, n = P.n;
-  const uint32_t S = (m + 63u) >> 6;  // strips
-  const uint32_t nw = max(1u, min(kPdpWaves, S));
-  if (wave >= nw) return;  // surplus waves leave; barriers wait for the waves that remain
-  const int64_t* dto = A.dgap + 4 * P.col;
-  const int64_t* dte = dto + n;
-  const int64_t* dgo = dto + 2 * n;
-  const int64_t* dge = dto + 3 * n;
-  const int64_t* ifirst = A.ifirst + P.col;
-  const int64_t* iext = A.iext + P.col;
-  int64_t* edges = A.edge + P.edge;  // two buffers of [j][M, D, I]
-  const uint64_t ebuf = 3ull * (n + 1);
+  const uint32_t nw = std::min(pdp_waves(m, n), (uint32_t)(blockDim.x >> 6));
   uint8_t* dir = A.dir + P.dir;
   uint8_t* strips = dir + pdp_row0_bytes(n);
-  // row 0: gaps in the sequence before its first residue (terminal costs).
-  // M(0,0) = 0 and D(0,1) comes from it; D(0,j), j >= 2, extends D(0,j-1);
-  // every other candidate starts from the unreachable value, far below any
-  // reachable one within the library's input limits, so row 0 is a prefix
-  // sum, taken 64 columns at a time across the lanes.
-  const int64_t neg = P.narrow ? (int64_t)pdp_neg<int32_t>() : pdp_neg<int64_t>();
-  if (wave == 0) {
-    int64_t* edge = edges + ebuf;  // buffer 1
-    int64_t carry = 0;             // D(0, base - 1)
-    for (uint32_t base = 0; base <= n; base += 64) {
-      const uint32_t j = base + lane;
-      int64_t x = 0;
-      if (j >= 1 && j <= n) x = j == 1 ? -dto[0] : -dte[j - 1];
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int64_t y = shfl_up64(x, d);
-        if ((int)lane >= d) x += y;
-      }
-      const int64_t Dj = carry + x;
-      if (j <= n) {
-        const int64_t M0 = j == 0 ? 0 : neg, D0 = j == 0 ? neg : Dj;
-        edge[3 * j] = M0;
-        edge[3 * j + 1] = D0;
-        edge[3 * j + 2] = neg;
-        dir[j] = (uint8_t)(j == 0 ? 0u : (1u | ((j == 1 ? 0u : 2u) << 2)));
-        if (m == 0 && j == n) {  // the cell (0, n) ends the alignment
-          s_fin[0] = M0;
-          s_fin[1] = D0;
-          s_fin[2] = neg;
-        }
-      }
-      carry = bcast64(Dj, 63);
+  if (P.lds) {  // every wave helps staging; the waves the DP does not use then leave
+    if (P.narrow && P.cost16) {
+      const PdpView<int32_t, int16_t> V = pdp_stage<int32_t, int16_t>(P, A, lds, sigma);
+      __syncthreads();
+      if (wave >= nw) return;
+      pdp_dp<int32_t, int32_t, int16_t>(P, A, V, dir, nw, s_fin);
+    } else if (P.narrow) {
+      const PdpView<int32_t, int32_t> V = pdp_stage<int32_t, int32_t>(P, A, lds, sigma);
+      __syncthreads();
+      if (wave >= nw) return;
+      pdp_dp<int32_t, int32_t, int32_t>(P, A, V, dir, nw, s_fin);
+    } else {
+      const PdpView<int64_t, int32_t> V = pdp_stage<int64_t, int32_t>(P, A, lds, sigma);
+      __syncthreads();
+      if (wave >= nw) return;
+      pdp_dp<int64_t, int64_t, int32_t>(P, A, V, dir, nw, s_fin);
     }
+  } else {
+    if (wave >= nw) return;  // barriers wait for the waves that remain
+    const PdpView<int64_t, int32_t> V{A.rec + P.col, A.cost + P.cost, A.edge + P.edge};
+    if (P.narrow) pdp_dp<int32_t, int64_t, int32_t>(P, A, V, dir, nw, s_fin);
+    else pdp_dp<int64_t, int64_t, int32_t>(P, A, V, dir, nw, s_fin);
   }
-  __threadfence_block();
-  __syncthreads();
-  if (P.narrow) pdp_strips<int32_t>(P, A, nw, s_fin);
-  else pdp_strips<int64_t>(P, A, nw, s_fin);
+  if (wave != 0) return;  // wave 0 traces back alone
   const int64_t fM = s_fin[0], fD = s_fin[1], fI = s_fin[2];
   int64_t best;
   int st = argmax3(fM, fD, fI, &best);
-  // trace back; every lane of every remaining wave walks the same path
-  // (uniform control flow), the choice bytes come through a 4 KB LDS window
-  // that wave 0 fills; wave 0 writes the alignment
+  // trace back: every lane walks the same path (uniform control flow); the
+  // choice bytes come through a 4 KB LDS window; lane 0 writes the alignment
   uint8_t* ops = A.ops + P.ops;
   uint32_t i = m, j = n, k = 0;
   int win = -2;        // window's region: -1 row 0, s >= 0 strip s
@@ -406,7 +501,7 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
     } else if (i == 0) {
       break;
     }
-    if (threadIdx.x == 0) ops[k] = (uint8_t)st;
+    if (lane == 0) ops[k] = (uint8_t)st;
     ++k;
     const int region = ci == 0 ? -1 : (int)((ci - 1) >> 6);
     const uint64_t idx = ci == 0 ? cj : (uint64_t)(cj + ((ci - 1) & 63u)) * 64 + ((ci - 1) & 63u);
@@ -415,12 +510,12 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
       const uint64_t size = region < 0 ? pdp_row0_bytes(n) : pdp_strip_bytes(n);
       win = region;
       wlo = idx >= 4032 ? ((idx - 4032) & ~(uint64_t)63) : 0;
-      __syncthreads();  // the previous window's reads are done
       const uint64_t off = wlo + (uint64_t)lane * 64;
-      if (wave == 0 && off < size) {
+      __syncthreads();  // the previous window's reads are done (wave 0 is the only wave left)
+      if (off < size) {
         const uint4* src = reinterpret_cast<const uint4*>(base + off);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) stage4[lane * 4 + q] = src[q];
+        for (int c = 0; c < 4; ++c) stage4[lane * 4 + c] = src[c];
       }
       __syncthreads();
     }
@@ -441,16 +536,14 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
   }
   __threadfence_block();
   __syncthreads();
-  if (wave == 0) {
-    for (uint32_t x = lane; x < k / 2; x += 64) {  // ops were written from the last column back
-      const uint8_t u = ops[x], v = ops[k - 1 - x];
-      ops[x] = v;
-      ops[k - 1 - x] = u;
-    }
+  for (uint32_t x = lane; x < k / 2; x += 64) {  // ops were written from the last column back
+    const uint8_t u = ops[x], v = ops[k - 1 - x];
+    ops[x] = v;
+    ops[k - 1 - x] = u;
   }
-  if (threadIdx.x == 0) {
-    A.score[blockIdx.x] = best;
-    A.nops[blockIdx.x] = (i == 0 && j == 0) ? k : 0xFFFFFFFFu;  // all ones: the walk stopped early
+  if (lane == 0) {
+    A.score[P.idx] = best;
+    A.nops[P.idx] = (i == 0 && j == 0) ? k : 0xFFFFFFFFu;  // all ones: the walk stopped early
   }
 }
 
@@ -514,6 +607,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     // every DP value is a sum of at most m + n + 1 terms of magnitude at most
     // K max(|S|, |gap cost|); int32 when that stays below 2^28
     d.narrow = ((uint64_t)m + n + 2) * (uint64_t)K * (uint64_t)std::max(smax, gmax) < (1ull << 28) ? 1u : 0u;
+    d.idx = p;
     d.seq = o_seq;
     d.rows = o_rows;
     d.cost = o_cost;
@@ -524,10 +618,10 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     d.ops = o_ops;
     o_seq += m;
     o_rows += (uint64_t)K * n;
-    o_cost += (uint64_t)sigma * n;
+    o_cost += (uint64_t)sigma * std::max(n, 1u);
     o_col += (uint64_t)n + 1;
     o_rowx += K;
-    o_edge += 6 * ((uint64_t)n + 1);  // two edge-row buffers
+    o_edge += 2 * ((uint64_t)n + 1);  // two edge-row buffers
     o_dir += pdp_dir_bytes((uint32_t)m, n);
     o_ops += m + n;
     nmax = std::max(nmax, n);
@@ -540,11 +634,41 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     return at;
   };
   const uint64_t b_probs = part(sizeof(PdpProb) * nprob), b_subst = part(4ull * sigma * sigma),
-                 b_seqs = part(o_seq), b_rows = part(o_rows), b_cost = part(4 * o_cost), b_w = part(4 * o_col),
-                 b_dgap = part(32 * o_col), b_if = part(8 * o_col), b_ie = part(8 * o_col), b_first = part(4 * o_rowx),
-                 b_last = part(4 * o_rowx), b_edge = part(8 * o_edge), b_dir = part(o_dir), b_ops = part(o_ops),
-                 b_score = part(8ull * nprob), b_nops = part(4ull * nprob);
+                 b_seqs = part(o_seq), b_rows = part(o_rows), b_cost = part(4 * o_cost),
+                 b_rec = part(sizeof(PdpRec<int64_t>) * o_col), b_first = part(4 * o_rowx),
+                 b_last = part(4 * o_rowx), b_edge = part(sizeof(PdpRec<int64_t>) * o_edge), b_dir = part(o_dir),
+                 b_ops = part(o_ops), b_score = part(8ull * nprob), b_nops = part(4ull * nprob);
   FAMSA_HIP(hipSetDevice(device));
+  // LDS: a problem whose records, costs and edge rows fit in half a CU's LDS
+  // (so that two problems share a CU) reads them from there; the launch
+  // reserves the largest such share for every workgroup
+  int max_lds = 0;
+  FAMSA_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+  hipFuncAttributes fa;
+  FAMSA_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&pdp_dp_kernel)));
+  const uint64_t lds_cap = (uint64_t)std::min(max_lds, (int)kMaxLds) / 2 > fa.sharedSizeBytes
+                               ? (uint64_t)std::min(max_lds, (int)kMaxLds) / 2 - fa.sharedSizeBytes
+                               : 0;
+  uint64_t lds_dyn = 0;
+  uint32_t waves = 1;  // the launch's workgroups have as many waves as the widest problem uses
+  for (PdpProb& d : pr) {
+    d.cost16 = d.narrow && (uint64_t)d.K * (uint64_t)smax < 32768 ? 1u : 0u;
+    const uint64_t need = pdp_lds_bytes(d.n, sigma, d.narrow ? 4 : 8, d.cost16 ? 2 : 4);
+    d.lds = need <= lds_cap ? 1u : 0u;
+    if (d.lds) lds_dyn = std::max(lds_dyn, need);
+    waves = std::max(waves, pdp_waves(d.m, d.n));
+  }
+  if (lds_dyn > 65536)
+    FAMSA_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&pdp_dp_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_dyn));
+  // launch order: the longest DP first (strips x sweep steps), so that the
+  // problem that bounds the launch starts at once
+  std::vector<uint32_t> order(nprob);
+  std::iota(order.begin(), order.end(), 0u);
+  auto span = [&](uint32_t p) { return (uint64_t)((pr[p].m + 63) / 64) * (pr[p].n + 64); };
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return span(a) > span(b); });
+  std::vector<PdpProb> launch(nprob);
+  for (uint32_t x = 0; x < nprob; ++x) launch[x] = pr[order[x]];
   hipStream_t st = nullptr;
   int rc = lib_stream(device, 0, &st);
   if (rc) return rc;
@@ -558,7 +682,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     const uint64_t rb = (uint64_t)pr[p].K * pr[p].n;
     if (rb) memcpy(hrows.data() + pr[p].rows, rows + rows_off[p], rb);
   }
-  FAMSA_HIP(hipMemcpyAsync(D + b_probs, pr.data(), sizeof(PdpProb) * nprob, hipMemcpyHostToDevice, st));
+  FAMSA_HIP(hipMemcpyAsync(D + b_probs, launch.data(), sizeof(PdpProb) * nprob, hipMemcpyHostToDevice, st));
   FAMSA_HIP(hipMemcpyAsync(D + b_subst, subst, 4ull * sigma * sigma, hipMemcpyHostToDevice, st));
   if (o_seq) FAMSA_HIP(hipMemcpyAsync(D + b_seqs, hseq.data(), o_seq, hipMemcpyHostToDevice, st));
   if (o_rows) FAMSA_HIP(hipMemcpyAsync(D + b_rows, hrows.data(), o_rows, hipMemcpyHostToDevice, st));
@@ -566,17 +690,18 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   A.seqs = D + b_seqs;
   A.rows = D + b_rows;
   A.cost = reinterpret_cast<int32_t*>(D + b_cost);
-  A.w = reinterpret_cast<int32_t*>(D + b_w);
-  A.dgap = reinterpret_cast<int64_t*>(D + b_dgap);
-  A.ifirst = reinterpret_cast<int64_t*>(D + b_if);
-  A.iext = reinterpret_cast<int64_t*>(D + b_ie);
+  A.rec = reinterpret_cast<PdpRec<int64_t>*>(D + b_rec);
   A.first = reinterpret_cast<int32_t*>(D + b_first);
   A.last = reinterpret_cast<int32_t*>(D + b_last);
-  A.edge = reinterpret_cast<int64_t*>(D + b_edge);
+  A.edge = reinterpret_cast<PdpRec<int64_t>*>(D + b_edge);
   A.dir = D + b_dir;
   A.ops = D + b_ops;
   A.score = reinterpret_cast<int64_t*>(D + b_score);
   A.nops = reinterpret_cast<uint32_t*>(D + b_nops);
+  A.To = gap_costs[0];
+  A.Te = gap_costs[1];
+  A.Go = gap_costs[2];
+  A.Ge = gap_costs[3];
   const PdpProb* dprobs = reinterpret_cast<const PdpProb*>(D + b_probs);
   hipEvent_t ev[2];
   FAMSA_HIP(hipEventCreate(&ev[0]));
@@ -584,11 +709,10 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   hipLaunchKernelGGL(pdp_rows_kernel, dim3(nprob), dim3(256), 0, st, dprobs, A);
   FAMSA_HIP(hipGetLastError());
   hipLaunchKernelGGL(pdp_cols_kernel, dim3(nprob, nmax / 256 + 1), dim3(256), 0, st, dprobs, A,
-                     reinterpret_cast<const int32_t*>(D + b_subst), sigma, gap_costs[0], gap_costs[1], gap_costs[2],
-                     gap_costs[3]);
+                     reinterpret_cast<const int32_t*>(D + b_subst), sigma);
   FAMSA_HIP(hipGetLastError());
   FAMSA_HIP(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL(pdp_dp_kernel, dim3(nprob), dim3(64 * kPdpWaves), 0, st, dprobs, A);
+  hipLaunchKernelGGL(pdp_dp_kernel, dim3(nprob), dim3(64 * waves), lds_dyn, st, dprobs, A, sigma);
   FAMSA_HIP(hipGetLastError());
   FAMSA_HIP(hipEventRecord(ev[1], st));
   std::vector<uint8_t> hops(o_ops ? o_ops : 1);

@@ -71,10 +71,14 @@ def test_negative_and_zero_costs():
 
 
 def test_long_problem():
-    # many strips and trace-back windows: m = 1500, n = 1300
+    # many strips and trace-back windows: m = 1500, n = 1300 (DP inputs too
+    # large for LDS, read from global memory), and m = 1500, n = 400 (24
+    # strips over the waves of one workgroup, DP inputs in LDS)
     rng = np.random.default_rng(51)
     S = inputs.synthetic_subst(20, 5)
-    check_batch([inputs.profile_problem(1500, 1300, 3, rng)], S, OP.scaled_gap_costs(1000, (9, 2, 12, 3)))
+    costs = OP.scaled_gap_costs(1000, (9, 2, 12, 3))
+    check_batch([inputs.profile_problem(1500, 1300, 3, rng)], S, costs)
+    check_batch([inputs.profile_problem(1500, 400, 5, rng), inputs.profile_problem(1300, 420, 2, rng)], S, costs)
 
 
 def test_rejects_bad_input():
@@ -90,13 +94,20 @@ def test_rejects_bad_input():
 
 def test_wide_values_and_mixed_batches():
     # scores and gap costs near the library's limits: the DP runs in int64
-    # for these problems and in int32 for the small ones of the same batch
+    # for these problems and in int32 for the small ones of the same batch;
+    # problems read their DP inputs from LDS or, when too wide, from global
+    # memory
     rng = np.random.default_rng(61)
     S = (inputs.synthetic_subst(20, 6).astype(np.int64) * 85).astype(np.int32)  # |S| up to 1020
     costs = (900_000, 30_000, 1_000_000, 50_000)
     probs = [inputs.profile_problem(int(rng.integers(60, 200)), int(rng.integers(60, 200)), int(rng.integers(20, 60)),
                                     rng) for _ in range(6)]
     check_batch(probs, S, costs)
+    # int64 problems too wide for their records, costs and edge rows to sit
+    # in LDS (they read them from global memory), beside ones that fit
+    wide = [inputs.profile_problem(int(rng.integers(550, 700)), int(rng.integers(550, 700)), int(rng.integers(20, 40)),
+                                   rng) for _ in range(2)]
+    check_batch(wide + probs[:2], S, costs)
     # one row and at most 40 columns and residues: below 2^28 even at these costs
     small = [inputs.profile_problem(int(rng.integers(1, 40)), int(rng.integers(1, 40)), 1, rng) for _ in range(6)]
     mixed = [p for pair in zip(probs, small) for p in pair]
