@@ -253,11 +253,26 @@ struct PdpView {
   PdpRec<E>* edge;       // two buffers of n + 1
 };
 
+// Edge rows keep kPdpPad unused records before column 0 and after column n:
+// over a sweep the writing lane's column runs from -63 to n + 63 and lane 0
+// reads up to column n + 64, so neither needs a bounds check.  Column j of
+// buffer b is record b * pdp_edge_cols(n) + kPdpPad + j.
+constexpr uint32_t kPdpPad = 64;
+__host__ __device__ inline uint64_t pdp_edge_cols(uint32_t n) { return (uint64_t)n + 1 + 2 * kPdpPad; }
+
 // LDS bytes a problem needs for its records, costs and edge rows.
 __host__ __device__ inline uint64_t pdp_lds_bytes(uint32_t n, uint32_t sigma, uint32_t value_bytes,
                                                   uint32_t cost_bytes) {
-  return 16ull * value_bytes / 4 * 3ull * (n + 1) + (uint64_t)cost_bytes * sigma * std::max(n, 1u);
+  return 16ull * value_bytes / 4 * ((n + 1) + 2 * pdp_edge_cols(n)) +
+         (uint64_t)cost_bytes * sigma * std::max(n, 1u);
 }
+
+// Wrapping int arithmetic: lanes outside the matrix run the same steps on
+// values that are never used, and those may leave the range.
+__device__ __forceinline__ int32_t wadd(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
+__device__ __forceinline__ int32_t wsub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
+__device__ __forceinline__ int64_t wadd(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
+__device__ __forceinline__ int64_t wsub(int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }
 
 // Row 0 (wave 0): gaps in the sequence before its first residue (terminal
 // costs).  M(0,0) = 0 and D(0,1) comes from it; D(0,j), j >= 2, extends
@@ -270,7 +285,7 @@ __device__ void pdp_row0(const PdpProb& P, const PdpArrays& A, const PdpView<E, 
                          int64_t* s_fin) {
   const uint32_t lane = threadIdx.x & 63u, n = P.n;
   constexpr T neg = pdp_neg<T>();
-  PdpRec<E>* edge = V.edge + (n + 1);
+  PdpRec<E>* edge = V.edge + pdp_edge_cols(n) + kPdpPad;
   int64_t carry = 0;  // D(0, base - 1)
   for (uint32_t base = 0; base <= n; base += 64) {
     const uint32_t j = base + lane;
@@ -318,50 +333,52 @@ __device__ void pdp_strips(const PdpProb& P, const PdpArrays& A, const PdpView<E
   const uint32_t w0 = wave * kPdpLag;  // this wave's first phase
   // this wave's current strip
   T Mc = neg, Dc = neg, Ic = neg, diag = neg, Oc = 0, Ec = 0;
-  bool active = false, writes_edge = false;
+  bool writes_edge = false;
   const C* crow = V.cost;
   const PdpRec<E>* ein = V.edge;
-  PdpRec<E>* eout = V.edge;
+  PdpRec<E>* eout = V.edge;   // this lane's column-0 record when it writes edges
   uint8_t* dstrip = strips;
   // what one step reads: this lane's cost, w, f and x at its column and the
   // edge record lane 0 needs
   struct Col {
-    T cost, w, f, x, eM, eD, eI;
+    C cost;  // widened where it is used, so that no step waits for the load it has just issued
+    T w, f, x, eM, eD, eI;
   };
   // the values at column jj (clamped: a lane outside the matrix reads a valid
-  // record and never uses it) and the edge record at column je
-  auto fetch = [&](int32_t jj, int32_t je) {
+  // record) and the edge record at column je, 0 <= je <= n + 64
+  auto fetch = [&](int32_t jj, uint32_t je) {
     const int32_t jc = min(max(jj, 0), (int32_t)n), jm = min(max(jj - 1, 0), nm1);
     const PdpRec<E> r = V.rec[jc];
-    const PdpRec<E> x = ein[min(max(je, 0), (int32_t)n)];
-    return Col{(T)crow[jm], (T)r.v[0], (T)r.v[1], (T)r.v[2], (T)x.v[0], (T)x.v[1], (T)x.v[2]};
+    const PdpRec<E> x = ein[je];
+    return Col{crow[jm], (T)r.v[0], (T)r.v[1], (T)r.v[2], (T)x.v[0], (T)x.v[1], (T)x.v[2]};
   };
+  // Every lane runs every step.  A lane before its column 0, past column n or
+  // below row m computes values nothing valid reads: its choice byte lands in
+  // a part of the strip the trace-back never visits, and the cell above of a
+  // valid cell is always valid.  At column 0 M and D are unreachable, so the
+  // values before column 0 do not reach it.
   auto step = [&](uint32_t t, const Col& c) {
     const T Mu = shr1(Mc, c.eM), Du = shr1(Dc, c.eD), Iu = shr1(Ic, c.eI);
-    const int32_t j = (int32_t)t - (int32_t)lane;
-    if (active && j >= 0 && j <= (int32_t)n) {
-      const T o = wmul(c.w, Oc), e = wmul(c.w, Ec);
-      T M = neg, D = neg, I, b;
-      int ds = 0;
-      if (j >= 1) {
-        M = diag + c.cost;
-        ds = argmax3(Mc - o, Ic - o, Dc - e, &D);
-      }
-      const int is = argmax3(Mu - c.f, Du - c.f, Iu - c.x, &I);
-      const int bk = argmax3(M, D, I, &b);
-      dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
-      diag = max(max(Mu, Du), Iu);  // the cell above is the next column's diagonal
-      Mc = M;
-      Dc = D;
-      Ic = I;
-      if (writes_edge) {
-        PdpRec<E> rr;
-        rr.v[0] = (E)M;
-        rr.v[1] = (E)D;
-        rr.v[2] = (E)I;
-        rr.v[3] = 0;
-        eout[j] = rr;
-      }
+    const bool j1 = t >= lane + 1;  // column t - lane >= 1
+    const T o = wmul(c.w, Oc), e = wmul(c.w, Ec);
+    T D1, I, b;
+    const int ds = argmax3(wsub(Mc, o), wsub(Ic, o), wsub(Dc, e), &D1);
+    const int is = argmax3(wsub(Mu, c.f), wsub(Du, c.f), wsub(Iu, c.x), &I);
+    const T M = j1 ? wadd(diag, (T)c.cost) : neg;
+    const T D = j1 ? D1 : neg;
+    const int bk = argmax3(M, D, I, &b);
+    dstrip[(uint64_t)t * 64] = (uint8_t)(bk | (ds << 2) | (is << 4));
+    diag = max(max(Mu, Du), Iu);  // the cell above is the next column's diagonal
+    Mc = M;
+    Dc = D;
+    Ic = I;
+    if (writes_edge) {
+      PdpRec<E> rr;
+      rr.v[0] = (E)M;
+      rr.v[1] = (E)D;
+      rr.v[2] = (E)I;
+      rr.v[3] = 0;
+      eout[t] = rr;
     }
   };
   Col cur{};  // the next step's values, loaded one step ahead
@@ -371,15 +388,16 @@ __device__ void pdp_strips(const PdpProb& P, const PdpArrays& A, const PdpView<E
       if (s < S && q < Q) {
         if (q == 0) {  // a new strip
           const uint32_t i = 64 * s + 1 + lane;
-          active = i <= m;
           const bool terminal = i == m;  // gaps after the sequence's last residue
           Oc = (T)(terminal ? A.To : A.Go);
           Ec = (T)(terminal ? A.Te : A.Ge);
-          const uint32_t a = active ? A.seqs[P.seq + i - 1] : 0u;
+          const uint32_t a = i <= m ? A.seqs[P.seq + i - 1] : 0u;
           crow = V.cost + (uint64_t)a * (nm1 + 1);
-          writes_edge = lane == 63 && s + 1 < S;
-          ein = V.edge + ((s + 1) & 1u) * (n + 1);
-          eout = V.edge + (s & 1u) * (n + 1);
+          // the last row of the strip writes its edge row; the last strip's
+          // row m writes one too, from which the final cell is read
+          writes_edge = lane == (s + 1 < S ? 63u : (m - 1) & 63u);
+          ein = V.edge + ((s + 1) & 1u) * pdp_edge_cols(n) + kPdpPad;
+          eout = V.edge + (s & 1u) * pdp_edge_cols(n) + kPdpPad - lane;
           dstrip = strips + (uint64_t)s * pdp_strip_bytes(n) + lane;
           Mc = Dc = Ic = diag = neg;
           cur = fetch(-(int32_t)lane, 0);
@@ -389,26 +407,28 @@ __device__ void pdp_strips(const PdpProb& P, const PdpArrays& A, const PdpView<E
         // two steps per iteration, the loads alternating between two sets of
         // registers, so that no step waits for the load it has just issued
         for (; t + 1 < t1; t += 2) {
-          const Col nx = fetch((int32_t)(t + 1) - (int32_t)lane, (int32_t)t + 1);
+          const Col nx = fetch((int32_t)(t + 1) - (int32_t)lane, t + 1);
           step(t, cur);
-          cur = fetch((int32_t)(t + 2) - (int32_t)lane, (int32_t)t + 2);
+          cur = fetch((int32_t)(t + 2) - (int32_t)lane, t + 2);
           step(t + 1, nx);
         }
         if (t < t1) {
-          const Col nx = fetch((int32_t)(t + 1) - (int32_t)lane, (int32_t)t + 1);
+          const Col nx = fetch((int32_t)(t + 1) - (int32_t)lane, t + 1);
           step(t, cur);
           cur = nx;
-        }
-        if (s + 1 == S && t1 == steps && lane == ((m - 1) & 63u)) {  // the cell (m, n)
-          s_fin[0] = (int64_t)Mc;
-          s_fin[1] = (int64_t)Dc;
-          s_fin[2] = (int64_t)Ic;
         }
       }
     }
     __threadfence_block();
     __syncthreads();
   }
+  if (S && threadIdx.x == 0) {  // the cell (m, n), from the last strip's edge row
+    const PdpRec<E> f = V.edge[((S - 1) & 1u) * pdp_edge_cols(n) + kPdpPad + n];
+    s_fin[0] = (int64_t)(T)f.v[0];
+    s_fin[1] = (int64_t)(T)f.v[1];
+    s_fin[2] = (int64_t)(T)f.v[2];
+  }
+  __syncthreads();
 }
 
 template <typename T, typename E, typename C>
@@ -427,7 +447,7 @@ __device__ PdpView<T, C> pdp_stage(const PdpProb& P, const PdpArrays& A, char* l
   const uint32_t n = P.n, n1 = std::max(n, 1u);
   PdpRec<T>* rec = reinterpret_cast<PdpRec<T>*>(lds);
   PdpRec<T>* edge = rec + (n + 1);
-  C* cost = reinterpret_cast<C*>(edge + 2 * (n + 1));
+  C* cost = reinterpret_cast<C*>(edge + 2 * pdp_edge_cols(n));
   const PdpRec<int64_t>* g = A.rec + P.col;
   for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) {
     const PdpRec<int64_t> x = g[j];
@@ -621,7 +641,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     o_cost += (uint64_t)sigma * std::max(n, 1u);
     o_col += (uint64_t)n + 1;
     o_rowx += K;
-    o_edge += 2 * ((uint64_t)n + 1);  // two edge-row buffers
+    o_edge += 2 * pdp_edge_cols(n);  // two edge-row buffers
     o_dir += pdp_dir_bytes((uint32_t)m, n);
     o_ops += m + n;
     nmax = std::max(nmax, n);
