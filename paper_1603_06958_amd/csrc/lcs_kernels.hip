@@ -84,6 +84,10 @@ __global__ void step_begin_kernel(StepCtl* ctl) {
 // A wave's 128-bit read of one (q, c) plane is 1 KB of consecutive bytes,
 // conflict free, and the symbol's part c * 1024 does not depend on W, so the
 // column streams store it pre-scaled and one SDWA v_add forms the address.
+// When W is not a multiple of 4 the last quad is read only as far as W
+// reaches (a 32-, 64- or 96-bit read at a 16-byte lane stride): lanes 16
+// apart then meet in the same banks, and such a read takes as many LDS
+// cycles as a full quad, no more.
 template <int SIG>
 __device__ __forceinline__ uint32_t lds_byte(uint32_t q, uint32_t c, uint32_t lane) {
   return q * (SIG * 1024u) + c * 1024u + lane * 16u;
