@@ -611,15 +611,17 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     if (n > FAMSA_LCS_MAX_LEN) return set_error(FAMSA_LCS_EINVAL, "problem %u: profile width %u", p, n);
     if (m && !seqs) return set_error(FAMSA_LCS_EINVAL, "seqs is NULL");
     if (n && !rows) return set_error(FAMSA_LCS_EINVAL, "rows is NULL");
-    for (uint64_t x = seq_off[p]; x < seq_off[p + 1]; ++x)
-      if (seqs[x] >= sigma)
-        return set_error(FAMSA_LCS_EINVAL, "problem %u: sequence code %u not below alphabet_size %u", p, seqs[x],
-                         sigma);
+    // codes: the largest sequence code, and the largest row code plus one
+    // (mod 256, so that a gap counts as 0), each taken in one pass
+    uint8_t smx = 0, rmx = 0;
+    for (uint64_t x = seq_off[p]; x < seq_off[p + 1]; ++x) smx = std::max(smx, seqs[x]);
     const uint8_t* r = rows ? rows + rows_off[p] : nullptr;
-    for (uint64_t x = 0; x < (uint64_t)K * n; ++x)
-      if (r[x] != FAMSA_PROFILE_GAP && r[x] >= sigma)
-        return set_error(FAMSA_LCS_EINVAL, "problem %u: profile code %u is neither a gap nor below %u", p, r[x],
-                         sigma);
+    for (uint64_t x = 0; x < (uint64_t)K * n; ++x) rmx = std::max(rmx, (uint8_t)(r[x] + 1u));
+    if (m && smx >= sigma)
+      return set_error(FAMSA_LCS_EINVAL, "problem %u: sequence code %u not below alphabet_size %u", p, smx, sigma);
+    if (rmx > sigma)
+      return set_error(FAMSA_LCS_EINVAL, "problem %u: profile code %u is neither a gap nor below %u", p, rmx - 1u,
+                       sigma);
     PdpProb& d = pr[p];
     d.m = (uint32_t)m;
     d.n = n;
@@ -696,16 +698,35 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   rc = mem.alloc(off);
   if (rc) return rc;
   uint8_t* D = mem.as<uint8_t>();
-  std::vector<uint8_t> hseq(o_seq ? o_seq : 1), hrows(o_rows ? o_rows : 1);
+  // sequences and rows go up in one copy each when the caller's arrays
+  // already hold them back to back in problem order, else through a packed
+  // host copy
+  bool seq_packed = true, rows_packed = true;
   for (uint32_t p = 0; p < nprob; ++p) {
-    if (pr[p].m) memcpy(hseq.data() + pr[p].seq, seqs + seq_off[p], pr[p].m);
-    const uint64_t rb = (uint64_t)pr[p].K * pr[p].n;
-    if (rb) memcpy(hrows.data() + pr[p].rows, rows + rows_off[p], rb);
+    seq_packed = seq_packed && seq_off[p] - seq_off[0] == pr[p].seq;
+    rows_packed = rows_packed && rows_off[p] - rows_off[0] == pr[p].rows;
+  }
+  std::vector<uint8_t> hseq, hrows;
+  const uint8_t* up_seq = o_seq ? seqs + seq_off[0] : nullptr;
+  const uint8_t* up_rows = o_rows ? rows + rows_off[0] : nullptr;
+  if (o_seq && !seq_packed) {
+    hseq.resize(o_seq);
+    for (uint32_t p = 0; p < nprob; ++p)
+      if (pr[p].m) memcpy(hseq.data() + pr[p].seq, seqs + seq_off[p], pr[p].m);
+    up_seq = hseq.data();
+  }
+  if (o_rows && !rows_packed) {
+    hrows.resize(o_rows);
+    for (uint32_t p = 0; p < nprob; ++p) {
+      const uint64_t rb = (uint64_t)pr[p].K * pr[p].n;
+      if (rb) memcpy(hrows.data() + pr[p].rows, rows + rows_off[p], rb);
+    }
+    up_rows = hrows.data();
   }
   FAMSA_HIP(hipMemcpyAsync(D + b_probs, launch.data(), sizeof(PdpProb) * nprob, hipMemcpyHostToDevice, st));
   FAMSA_HIP(hipMemcpyAsync(D + b_subst, subst, 4ull * sigma * sigma, hipMemcpyHostToDevice, st));
-  if (o_seq) FAMSA_HIP(hipMemcpyAsync(D + b_seqs, hseq.data(), o_seq, hipMemcpyHostToDevice, st));
-  if (o_rows) FAMSA_HIP(hipMemcpyAsync(D + b_rows, hrows.data(), o_rows, hipMemcpyHostToDevice, st));
+  if (o_seq) FAMSA_HIP(hipMemcpyAsync(D + b_seqs, up_seq, o_seq, hipMemcpyHostToDevice, st));
+  if (o_rows) FAMSA_HIP(hipMemcpyAsync(D + b_rows, up_rows, o_rows, hipMemcpyHostToDevice, st));
   PdpArrays A;
   A.seqs = D + b_seqs;
   A.rows = D + b_rows;
