@@ -106,25 +106,41 @@ __device__ __forceinline__ int argmax3(T x0, T x1, T x2, T* best) {
   return k;
 }
 
-// A wave per row: first and last column holding a residue (n and -1 if none).
+// A wave per row: first and last column holding a residue (n and -1 if
+// none).  Block (p, y) takes the rows 16 y' .. 16 y' + 15 of problem p for
+// y' = y, y + gridDim.y, ..., four per wave; a wave reads 256 columns of a
+// row at a time (four loads in flight per lane).
+constexpr uint32_t kRowsPerBlock = 16;
+
 __global__ __launch_bounds__(256) void pdp_rows_kernel(const PdpProb* __restrict__ probs, PdpArrays A) {
   const PdpProb P = probs[blockIdx.x];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (uint32_t s = wave; s < P.K; s += nw) {
-    const uint8_t* row = A.rows + P.rows + (uint64_t)s * P.n;
-    int32_t f = (int32_t)P.n, l = -1;
-    for (uint32_t c0 = 0; c0 < P.n; c0 += 64) {
-      const uint32_t c = c0 + lane;
-      const bool res = c < P.n && row[c] != kGap;
-      const uint64_t b = __ballot(res);
-      if (b) {
-        if (f == (int32_t)P.n) f = (int32_t)(c0 + __builtin_ctzll(b));
-        l = (int32_t)(c0 + 63 - __builtin_clzll(b));
+  for (uint32_t y = blockIdx.y; y * kRowsPerBlock < P.K; y += gridDim.y) {
+    const uint32_t s1 = min(P.K, (y + 1) * kRowsPerBlock);
+    for (uint32_t s = y * kRowsPerBlock + wave; s < s1; s += nw) {  // wave-uniform: the ballots see every lane
+      const uint8_t* row = A.rows + P.rows + (uint64_t)s * P.n;
+      int32_t f = (int32_t)P.n, l = -1;
+      for (uint32_t c0 = 0; c0 < P.n; c0 += 256) {
+        uint32_t x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t c = c0 + 64u * u + lane;
+          x[u] = c < P.n ? row[c] : kGap;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint64_t b = __ballot(x[u] != kGap);
+          if (b) {
+            const uint32_t base = c0 + 64u * u;
+            if (f == (int32_t)P.n) f = (int32_t)(base + __builtin_ctzll(b));
+            l = (int32_t)(base + 63 - __builtin_clzll(b));
+          }
+        }
       }
-    }
-    if (lane == 0) {
-      A.first[P.rowx + s] = f;
-      A.last[P.rowx + s] = l;
+      if (lane == 0) {
+        A.first[P.rowx + s] = f;
+        A.last[P.rowx + s] = l;
+      }
     }
   }
 }
@@ -144,17 +160,33 @@ __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict
   if (j > P.n) return;
   const uint8_t* rows = A.rows + P.rows;
   uint32_t cTA = 0, cTO = 0, cIA = 0, cIO = 0;  // boundary situations: terminal/inside x next to a gap/opening
-  for (uint32_t s = 0; s < P.K; ++s) {
-    const uint8_t* row = rows + (uint64_t)s * P.n;
-    const uint32_t x = j < P.n ? row[j] : kGap;
-    if (x != kGap) ++hist[x][tid];
-    const bool gap_right = j < P.n && x == kGap;
-    const bool gap_left = j >= 1 && row[j - 1] == kGap;
-    const int32_t f = A.first[P.rowx + s], l = A.last[P.rowx + s];
-    const bool inside = f < (int32_t)j && l >= (int32_t)j;  // residues on both sides of the boundary
-    const bool adj = gap_left || gap_right;
-    if (inside) { if (adj) ++cIA; else ++cIO; }
-    else { if (adj) ++cTA; else ++cTO; }
+  // eight rows at a time, their loads issued together
+  constexpr uint32_t kU = 8;
+  for (uint32_t s0 = 0; s0 < P.K; s0 += kU) {
+    uint32_t xr[kU], xl[kU];
+    int32_t fr[kU], lr[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      const uint32_t s = s0 + u;
+      const bool ok = s < P.K;
+      const uint8_t* row = rows + (uint64_t)s * P.n;
+      xr[u] = ok && j < P.n ? row[j] : kGap;
+      xl[u] = ok && j >= 1 ? row[j - 1] : 0u;
+      fr[u] = ok ? A.first[P.rowx + s] : 0;
+      lr[u] = ok ? A.last[P.rowx + s] : 0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      if (s0 + u >= P.K) break;
+      const uint32_t x = xr[u];
+      if (x != kGap) ++hist[x][tid];
+      const bool gap_right = j < P.n && x == kGap;
+      const bool gap_left = j >= 1 && xl[u] == kGap;
+      const bool inside = fr[u] < (int32_t)j && lr[u] >= (int32_t)j;  // residues on both sides of the boundary
+      const bool adj = gap_left || gap_right;
+      if (inside) { if (adj) ++cIA; else ++cIO; }
+      else { if (adj) ++cTA; else ++cTO; }
+    }
   }
   PdpRec<int64_t>* rec = A.rec + P.col;
   rec[j].v[1] = (int64_t)cTA * A.Te + (int64_t)cTO * A.To + (int64_t)cIA * A.Ge + (int64_t)cIO * A.Go;
@@ -599,7 +631,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   for (int c = 0; c < 4; ++c) gmax = std::max<int64_t>(gmax, gap_costs[c] < 0 ? -gap_costs[c] : gap_costs[c]);
   std::vector<PdpProb> pr(nprob);
   uint64_t o_seq = 0, o_rows = 0, o_cost = 0, o_col = 0, o_rowx = 0, o_edge = 0, o_dir = 0, o_ops = 0;
-  uint32_t nmax = 0;
+  uint32_t nmax = 0, kmax = 1;
   for (uint32_t p = 0; p < nprob; ++p) {
     if (seq_off[p + 1] < seq_off[p]) return set_error(FAMSA_LCS_EINVAL, "seq_off decreases at %u", p);
     const uint64_t m = seq_off[p + 1] - seq_off[p];
@@ -647,6 +679,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     o_dir += pdp_dir_bytes((uint32_t)m, n);
     o_ops += m + n;
     nmax = std::max(nmax, n);
+    kmax = std::max(kmax, K);
   }
   // one device allocation, 256-byte aligned parts
   uint64_t off = 0;
@@ -747,7 +780,8 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   hipEvent_t ev[2];
   FAMSA_HIP(hipEventCreate(&ev[0]));
   FAMSA_HIP(hipEventCreate(&ev[1]));
-  hipLaunchKernelGGL(pdp_rows_kernel, dim3(nprob), dim3(256), 0, st, dprobs, A);
+  hipLaunchKernelGGL(pdp_rows_kernel, dim3(nprob, std::min(64u, (kmax + kRowsPerBlock - 1) / kRowsPerBlock)),
+                     dim3(256), 0, st, dprobs, A);
   FAMSA_HIP(hipGetLastError());
   hipLaunchKernelGGL(pdp_cols_kernel, dim3(nprob, nmax / 256 + 1), dim3(256), 0, st, dprobs, A,
                      reinterpret_cast<const int32_t*>(D + b_subst), sigma);
