@@ -3,6 +3,8 @@ workloads (every value of every 1024-row tile), for the GPU test that checks
 the HIP path against them value for value.
 
     python tests/golden/make_oracle_digests.py c2 c3 [--workers N]
+    python tests/golden/make_oracle_digests.py c3 --families 25 --add
+
 
 Only the oracle (oracle.tile_expected: the textbook DP, one pair at a time)
 computes the values; the inputs come from the seeded generator.  A digest is
@@ -10,8 +12,9 @@ blake2b (16 bytes) over the tile's int32 values in tile order (row i holds
 LCS(i, j), j = i+1..k-1, rows back to back), little-endian.
 
 Families with more than MAX_FAMILY_CELLS all-pairs DP cells are left out (in
-c3 the largest, 74% of its cells, which would take the oracle hours on a few
-cores); the file lists them, and every other family's tiles are there.
+c3 the largest, 74% of its cells, which takes the oracle hours on a few
+cores) unless named with --families; --add merges the new tiles into the
+file already written.  The file lists the families it does not hold.
 """
 import argparse
 import hashlib
@@ -57,12 +60,13 @@ def family_cells(b, f):
     return (int(lens.sum()) ** 2 - int((lens * lens).sum())) // 2
 
 
-def digests(name, workers):
+def digests(name, workers, families=None):
     b = _batch(name)
-    units, tiles, skipped = [], [], []
+    units, tiles = [], []
     for f in range(b.nfam):
-        if family_cells(b, f) > MAX_FAMILY_CELLS:
-            skipped.append(f)
+        if families is not None and f not in families:
+            continue
+        if families is None and family_cells(b, f) > MAX_FAMILY_CELLS:
             continue
         k = int(b.fam_off[f + 1] - b.fam_off[f])
         for t0 in range(0, k, TILE_ROWS):
@@ -91,18 +95,32 @@ def digests(name, workers):
         parts = [out[(name, f, c0, min(r1, c0 + CHUNK))] for c0 in range(r0, r1, CHUNK)]
         v = np.concatenate(parts).astype("<i4") if parts else np.zeros(0, "<i4")
         lines.append(f"{f} {r0} {r1} {v.size} {hashlib.blake2b(v.tobytes(), digest_size=16).hexdigest()}")
-    return lines, skipped
+    return lines
+
+
+def read_lines(path):
+    if not os.path.exists(path):
+        return []
+    return [ln.rstrip("\n") for ln in open(path) if ln.strip() and not ln.startswith("#")]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("names", nargs="+", choices=["c2", "c3"])
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--families", type=int, nargs="+", help="only these families (whatever their size)")
+    ap.add_argument("--add", action="store_true", help="merge into the file already written")
     a = ap.parse_args()
     oracle.build()
     for name in a.names:
-        lines, skipped = digests(name, a.workers)
         path = os.path.join(HERE, f"oracle_digests_{name}.txt")
+        new = digests(name, a.workers, set(a.families) if a.families else None)
+        have = {tuple(ln.split()[:3]): ln for ln in (read_lines(path) if a.add else [])}
+        have.update({tuple(ln.split()[:3]): ln for ln in new})
+        lines = [have[key] for key in sorted(have, key=lambda t: tuple(int(x) for x in t))]
+        held = {int(ln.split()[0]) for ln in lines}
+        b = _batch(name)
+        skipped = [f for f in range(b.nfam) if f not in held and int(b.fam_off[f + 1] - b.fam_off[f]) > 1]
         with open(path, "w") as fh:
             fh.write(f"# oracle per-tile digests: {name}, generator version {inputs.GENERATOR_VERSION}, "
                      f"tile_rows {TILE_ROWS}\n# written by tests/golden/make_oracle_digests.py {name}\n"
