@@ -95,7 +95,9 @@ typedef struct famsa_lcs_options {
   uint32_t cols_per_item;  /* columns per work item, 0 = tuned/default */
   uint64_t step_values;    /* int32 values per launch step (several tiles), 0 = default (2^27) */
   uint64_t step_cells;     /* server only: cells |A||B| per scheduler step, which bounds how long a
-                              step runs and so how long a new job waits; a step still takes at
+                              step runs and so how long a new job waits; the server's tiles then
+                              also hold at most this many cells (fewer than tile_rows rows for
+                              jobs of long rows, at least one row), and a step still takes at
                               least one tile; 0 = no bound (plans ignore it) */
 } famsa_lcs_options;
 
@@ -381,7 +383,9 @@ int famsa_lcs_server_create(const famsa_lcs_options* opt, famsa_lcs_server_t** o
 int famsa_lcs_server_submit(famsa_lcs_server_t* srv, const uint8_t* codes, const uint64_t* seq_off,
                             uint32_t nseq, uint32_t* job_id);
 /* Admit queued jobs that fit, run one step over all admitted jobs, deliver its
- * tiles (tile.family = job id, per-job tile_index), retire finished jobs.
+ * tiles (tile.family = job id, per-job tile_index; a job's tiles cover its
+ * rows in order, tile_rows at a time, or fewer under a step_cells bound),
+ * retire finished jobs.
  * *active receives the number of jobs still admitted or queued. */
 int famsa_lcs_server_step(famsa_lcs_server_t* srv, famsa_lcs_tile_fn fn, void* user, uint32_t* active);
 /* Job state: 0 queued, 1 admitted, 2 done. */

@@ -5,7 +5,8 @@
 // sequences and masks then stay on the device until its last tile is
 // delivered.  Every scheduler step gathers pending tiles of all admitted
 // jobs -- jobs with the least remaining work first, a job whose whole
-// triangle fits the step as one family-mode unit, larger jobs tile by tile --
+// triangle fits the step (values and cells) as one family-mode unit, larger
+// jobs tile by tile --
 // into one launch per length class.  The step's sequence index space is
 // assembled from the jobs' own device arrays: per-sequence byte addresses
 // and mask addresses are absolute, so the kernels read every job in place.
@@ -387,22 +388,32 @@ int famsa_lcs_server_submit(famsa_lcs_server_t* s, const uint8_t* codes, const u
   for (uint32_t i = 0; i < nseq; ++i) L[i] = j->off[i + 1] - j->off[i];
   std::vector<uint64_t> suffix(nseq + 1, 0);
   for (uint32_t i = nseq; i-- > 0;) suffix[i] = suffix[i + 1] + L[i];
-  for (uint32_t r0 = 0; r0 < nseq; r0 += R) {
-    const uint32_t r1 = std::min(nseq, r0 + R);
+  // Tiles of at most R rows and, with a cell bound per step, at most that
+  // many cells (a tile holds at least one row): a step that a long job's
+  // tile would fill alone then still ends in about the bounded time, so a
+  // job that arrives meanwhile does not wait behind it.
+  for (uint32_t r0 = 0; r0 < nseq;) {
+    uint32_t r1 = r0;
+    uint64_t c = 0;
+    do {
+      c += L[r1] * suffix[r1 + 1];
+      ++r1;
+    } while (r1 < nseq && r1 - r0 < R && (!s->step_cells || c + L[r1] * suffix[r1 + 1] <= s->step_cells));
     const uint64_t cnt = tri_rows(nseq, r0, r1);
     j->tiles.push_back(Job::T{r0, r1, cnt});
-    uint64_t c = 0;
-    for (uint32_t i = r0; i < r1; ++i) c += L[i] * suffix[i + 1];
     j->tile_cells.push_back(c);
     j->remaining_cells += c;
     tri += cnt;
+    r0 = r1;
   }
   for (const auto& t : j->tiles)
     if (t.count > s->step_values)
       return set_error(FAMSA_LCS_ENOMEM, "a %u-row tile of this job holds %llu values, more than the step buffer's "
                        "%llu; use fewer tile_rows or a larger step_values",
                        s->opt.tile_rows, (unsigned long long)t.count, (unsigned long long)s->step_values);
-  j->whole = tri <= s->step_values;
+  // one family-mode unit only if it also keeps within the step's cell bound:
+  // a step that such a job fills alone would otherwise run as long as the job
+  j->whole = tri <= s->step_values && (!s->step_cells || j->remaining_cells <= s->step_cells);
   j->id = s->next_id++;
   *job_id = j->id;
   if (j->tiles.empty()) {  // an empty job is done at once

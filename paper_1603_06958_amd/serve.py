@@ -88,10 +88,9 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
     n = len(jobs)
     order = sorted(range(n), key=lambda i: jobs[i].arrival_s)
     ids: Dict[int, int] = {}
-    tiles_left: Dict[int, int] = {}
+    rows_left: Dict[int, int] = {}  # a job's tiles cover its rows; it is done when all have come
     done_t: Dict[int, float] = {}
     submit_t: Dict[int, float] = {}
-    tile_rows = server_opts.get("tile_rows", 1024)
     step_jobs: List[set] = []  # job ids whose tiles each step call delivered
 
     def fn(t):
@@ -99,8 +98,8 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
         step_jobs[-1].add(j)
         if on_tile:
             on_tile(j, t)
-        tiles_left[j] -= 1
-        if tiles_left[j] == 0:
+        rows_left[j] -= int(t.row_end) - int(t.row_begin)
+        if rows_left[j] == 0:
             done_t[j] = time.perf_counter()
         return 0
 
@@ -109,23 +108,24 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
     active = 0
     while nxt < n or active:
         now = time.perf_counter() - t0
+        submitted = 0
         while nxt < n and (not realtime or jobs[order[nxt]].arrival_s <= now):
             i = order[nxt]
             b = jobs[i].batch
             jid = srv.submit(b.codes, b.seq_off)
             ids[jid] = i
-            k = b.nseq
-            tiles_left[jid] = (k + tile_rows - 1) // tile_rows
+            rows_left[jid] = b.nseq
             submit_t[jid] = t0 + (jobs[i].arrival_s if realtime else 0.0)
-            if tiles_left[jid] == 0:
+            if rows_left[jid] == 0:
                 done_t[jid] = time.perf_counter()
             nxt += 1
-        if nxt < n and active == 0 and realtime:
+            submitted += 1
+        if nxt < n and active == 0 and not submitted and realtime:
+            # nothing to run: wait for the next arrival (a job submitted just
+            # now is stepped at once, not after this wait)
             wait = jobs[order[nxt]].arrival_s - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.05))
-            step_jobs.append(set())
-            active = srv.step(fn)
             continue
         step_jobs.append(set())
         active = srv.step(fn)
@@ -144,12 +144,12 @@ def run_jobs(jobs: List[inputs.ServeJob], on_tile: Optional[Callable] = None, re
 
 # Serving steps are kept small so that a new job waits for little work ahead of
 # it: at most 2^24 values (64 MiB per buffer) and 2^41 cells (about 4 ms of
-# device time) per step, and 256-row tiles, which hold families of up to
-# ~65,000 sequences.  A job arriving while step s runs joins step s + 2 (step
-# s + 1 is already issued), so its wait is about two steps.  On the c5 mix the
-# cell bound and the smaller tiles take the median latency from 25 ms to 15 ms
-# and the median slowdown over the job's own service time from 8.4 to 3.6, at
-# the same throughput.
+# device time) per step, and tiles of at most 256 rows and 2^41 cells, which
+# hold families of up to ~65,000 sequences.  A job arriving while step s runs
+# joins step s + 2 (step s + 1 is already issued), so its wait is about two
+# steps.  On the c5 mix (200 jobs at the frozen rate) 2^40-cell steps give a
+# median latency of 6.3 ms but a p99 of 511 ms and 10% less capacity; 2^41
+# gives 8.9 ms and 386 ms; 2^42 gives 14 ms and 292 ms and 7% more capacity.
 SERVE_STEP_VALUES = 1 << 24
 SERVE_STEP_CELLS = 1 << 41
 SERVE_TILE_ROWS = 256

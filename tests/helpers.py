@@ -53,6 +53,35 @@ def digest(a: np.ndarray) -> bytes:
         return hashlib.blake2b(np.ascontiguousarray(a).tobytes(), digest_size=16).digest()
 
 
+class RowStream:
+    """A family's values as one stream, whatever the tiles: tiles must come in
+    row order and cover rows 0..k without gaps; the digest is that of the
+    upper triangle row by row (row i holds LCS(i, j), j = i+1..k-1)."""
+
+    def __init__(self, k):
+        self.k = k
+        self.next = 0
+        self.tiles = 0
+        try:
+            import xxhash
+            self.h = xxhash.xxh3_128()
+        except ImportError:
+            import hashlib
+            self.h = hashlib.blake2b(digest_size=16)
+
+    def feed(self, t):
+        r0, r1 = int(t.row_begin), int(t.row_end)
+        assert r0 == self.next and r1 > r0, f"tile [{r0},{r1}) after row {self.next}"
+        import paper_1603_06958_amd.binding as B
+        self.h.update(np.ascontiguousarray(B.tile_array(t)).view(np.uint8))
+        self.next = r1
+        self.tiles += 1
+
+    def digest(self):
+        assert self.next == self.k, f"rows up to {self.next} of {self.k}"
+        return self.h.digest()
+
+
 class Sampler:
     """Tile callback keeping `per_tile` seeded samples (and bound checks)."""
 

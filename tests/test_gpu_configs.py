@@ -2,8 +2,8 @@
 c4, and the c5 serving jobs): seeded samples of every tile checked against
 the oracle one pair at a time, plus 0 <= LCS <= min(|A|, |B|) over every
 value of every tile; every value of the batched kernels also equals the
-plain kernel's (c2, c3, c4: per-tile digests), and every c5 job's tiles are
-the same in the serving mix as when the job runs alone; on c4 the host
+plain kernel's (c2, c3, c4: per-tile digests), and every c5 job's values
+are the same in the serving mix as when the job runs alone; on c4 the host
 SLINK consumer and the GPU spanning-tree consumer, both fed the GPU's tiles,
 give the same merge heights, and every tree edge's LCS is the oracle's."""
 from fractions import Fraction
@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import Sampler, check_all_tiles, digest
+from helpers import RowStream, Sampler, check_all_tiles, digest
 from paper_1603_06958_amd import binding as B
 from paper_1603_06958_amd import inputs
 
@@ -129,23 +129,35 @@ def test_c4_two_streams_with_graphs_equals_plain(c4_plain):
 def test_c5_jobs_sampled_in_the_serving_configuration():
     # every job of the serving workload (all 200 jobs of the bench's mix)
     # through the server as bench.py runs it (2^24-value, 2^41-cell steps,
-    # 256-row tiles), arrivals replayed at once; every tile of every job
-    # equals the job's tile when it runs alone (digests), seeded samples
-    # match the oracle and every value is within [0, min length]
+    # tiles of at most 256 rows and 2^41 cells), arrivals replayed at once;
+    # every job's values, row by row, equal the job's when it runs alone
+    # (stream digests, whatever the tile boundaries), seeded samples match
+    # the oracle, every value is within [0, min length], and no tile passes
+    # the cell bound unless it is one row
     import os
     from paper_1603_06958_amd import serve
     jobs = inputs.c5(seed=4, njobs=200, rate_per_s=serve.C5_RATE_PER_S,
                      workers=min(16, len(os.sched_getaffinity(0))))
     samplers = {}
-    mixed = {}
+    streams = {}
+    row_cells = {}  # per job: cells of each row's pairs, L_i * (L_{i+1} + ... + L_{k-1})
+    over = []
 
     def on_tile(jid, t):
+        b = jobs[r_ids[jid]].batch
         if jid not in samplers:
-            samplers[jid] = Sampler(jobs[r_ids[jid]].batch, per_tile=4, seed=jid)
+            samplers[jid] = Sampler(b, per_tile=4, seed=jid)
+            streams[jid] = RowStream(b.nseq)
+            L = b.lengths().astype(np.int64)
+            after = np.concatenate([np.cumsum(L[::-1])[::-1][1:], [0]])
+            row_cells[jid] = L * after
         local = B.Tile.from_buffer_copy(t)  # the job's own batch holds one family
         local.family = 0
-        mixed[(jid, int(t.row_begin), int(t.row_end))] = digest(B.tile_array(t))
+        streams[jid].feed(t)
         samplers[jid](local)
+        r0, r1 = int(t.row_begin), int(t.row_end)
+        if r1 - r0 > 1 and int(row_cells[jid][r0:r1].sum()) > serve.SERVE_STEP_CELLS:
+            over.append((jid, r0, r1))
 
     r_ids = {}
     srv = serve.Server(step_values=serve.SERVE_STEP_VALUES, step_cells=serve.SERVE_STEP_CELLS,
@@ -161,16 +173,20 @@ def test_c5_jobs_sampled_in_the_serving_configuration():
     srv.close()
     assert max(len(x) for x in per_step) >= 2  # tiles of several jobs in one step
     assert len(samplers) == len(jobs)
+    assert not over, f"tiles over the cell bound: {over[:3]}"
+    # the cell bound cut some job's tiles below 256 rows
+    assert any(streams[jid].tiles > (jobs[i].batch.nseq + 255) // 256 for jid, i in r_ids.items())
     total = 0
     for jid, smp in samplers.items():
         assert smp.count == jobs[r_ids[jid]].batch.pairs()
         total += smp.check()
     assert total >= 1000
-    # each job alone, through a plan with the same tile rows
+    # each job alone, through a plan with 256-row tiles
     for n, (jid, i) in enumerate(r_ids.items()):
-        alone = run_hashed(jobs[i].batch, tile_rows=serve.SERVE_TILE_ROWS, step_values=serve.SERVE_STEP_VALUES)
-        assert len(alone) == len([key for key in mixed if key[0] == jid])
-        for (f, r0, r1), h in alone.items():
-            assert mixed[(jid, r0, r1)] == h, (jid, r0)
+        alone = RowStream(jobs[i].batch.nseq)
+        with B.Plan.from_batch(jobs[i].batch, tile_rows=serve.SERVE_TILE_ROWS,
+                               step_values=serve.SERVE_STEP_VALUES) as p:
+            p.run(lambda t: (alone.feed(t), 0)[1])
+        assert streams[jid].digest() == alone.digest(), jid
         if n % 50 == 49:
-            print(f"c5: {n + 1} jobs alone equal their tiles in the mix", flush=True)
+            print(f"c5: {n + 1} jobs alone equal their values in the mix", flush=True)

@@ -1,5 +1,6 @@
-"""Serving: every job's tiles are bit-exact against the oracle and identical
-to the same job run alone through a plan; a budget that fits one job at a
+"""Serving: every job's values are bit-exact against the oracle and identical
+to the same job run alone through a plan (tiles of tile_rows rows, or fewer
+under a cell bound); a budget that fits one job at a
 time queues jobs instead of failing; a job that can never fit is refused."""
 import numpy as np
 import pytest
@@ -53,11 +54,24 @@ def test_serving_matches_oracle_and_alone(R, step_values, step_cells, realtime):
         k = b.nseq
         with B.Plan.from_batch(b, tile_rows=R) as p:
             alone = p.collect()
-        for r0 in range(0, k, R):
-            r1 = min(k, r0 + R)
-            mix = got[(jid, r0, r1)]
-            assert np.array_equal(mix, alone[(0, r0, r1)]), (jid, r0)
-            assert np.array_equal(mix, oracle.tile_expected(b.codes, b.seq_off, 0, k, r0, r1)), (jid, r0)
+        keys = sorted(key for key in got if key[0] == jid)
+        # the job's tiles cover its rows in order; R rows each without a
+        # cell bound, at most R rows and the bound's cells (or one row) with it
+        assert keys[0][1] == 0 and keys[-1][2] == k and all(a[2] == c[1] for a, c in zip(keys, keys[1:]))
+        L = b.lengths().astype(np.int64)
+        cells = L * np.concatenate([np.cumsum(L[::-1])[::-1][1:], [0]])
+        for _, r0, r1 in keys:
+            assert r1 - r0 <= R
+            if step_cells:
+                assert r1 - r0 == 1 or int(cells[r0:r1].sum()) <= step_cells, (jid, r0, r1)
+            else:
+                assert r0 % R == 0
+        mix = np.concatenate([got[key] for key in keys])
+        whole = np.concatenate([alone[key] for key in sorted(alone)])
+        assert np.array_equal(mix, whole), jid
+        assert np.array_equal(mix, oracle.tile_expected(b.codes, b.seq_off, 0, k, 0, k)), jid
+    if step_cells:  # the bound cut some tile below R rows
+        assert any(key[2] - key[1] < R and key[2] != jobs[ids[key[0]]].batch.nseq for key in got)
 
 
 def test_small_budget_queues():
