@@ -306,6 +306,18 @@ __device__ __forceinline__ int32_t wsub(int32_t a, int32_t b) { return (int32_t)
 __device__ __forceinline__ int64_t wadd(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
 __device__ __forceinline__ int64_t wsub(int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }
 
+// argmax3(a - s, b - s, c) with one subtraction: a - s and b - s compare as
+// a and b (no reachable value is near the ends of the range), so the larger
+// of a and b is taken first.
+template <typename T>
+__device__ __forceinline__ int argmax3_sub(T a, T b, T s, T c, T* best) {
+  const int k1 = b > a ? 1 : 0;
+  const T b01 = wsub(max(a, b), s);
+  const bool k2 = c > b01;
+  *best = k2 ? c : b01;
+  return k2 ? 2 : k1;
+}
+
 // Row 0 (wave 0): gaps in the sequence before its first residue (terminal
 // costs).  M(0,0) = 0 and D(0,1) comes from it; D(0,j), j >= 2, extends
 // D(0,j-1); every other candidate starts from the unreachable value, far
@@ -379,7 +391,8 @@ __device__ void pdp_strips(const PdpProb& P, const PdpArrays& A, const PdpView<E
   // the values at column jj (clamped: a lane outside the matrix reads a valid
   // record) and the edge record at column je, 0 <= je <= n + 64
   auto fetch = [&](int32_t jj, uint32_t je) {
-    const int32_t jc = min(max(jj, 0), (int32_t)n), jm = min(max(jj - 1, 0), nm1);
+    // (a negative column, as unsigned, clamps to the top)
+    const uint32_t jc = min((uint32_t)jj, n), jm = min((uint32_t)(jj - 1), (uint32_t)nm1);
     const PdpRec<E> r = V.rec[jc];
     const PdpRec<E> x = ein[je];
     return Col{crow[jm], (T)r.v[0], (T)r.v[1], (T)r.v[2], (T)x.v[0], (T)x.v[1], (T)x.v[2]};
@@ -394,8 +407,8 @@ __device__ void pdp_strips(const PdpProb& P, const PdpArrays& A, const PdpView<E
     const bool j1 = t >= lane + 1;  // column t - lane >= 1
     const T o = wmul(c.w, Oc), e = wmul(c.w, Ec);
     T D1, I, b;
-    const int ds = argmax3(wsub(Mc, o), wsub(Ic, o), wsub(Dc, e), &D1);
-    const int is = argmax3(wsub(Mu, c.f), wsub(Du, c.f), wsub(Iu, c.x), &I);
+    const int ds = argmax3_sub(Mc, Ic, o, wsub(Dc, e), &D1);
+    const int is = argmax3_sub(Mu, Du, c.f, wsub(Iu, c.x), &I);
     const T M = j1 ? wadd(diag, (T)c.cost) : neg;
     const T D = j1 ? D1 : neg;
     const int bk = argmax3(M, D, I, &b);
