@@ -145,11 +145,14 @@ __global__ __launch_bounds__(256) void pdp_rows_kernel(const PdpProb* __restrict
   }
 }
 
-// blockIdx.y picks 256 columns (boundaries) of problem blockIdx.x.
+// blockIdx.y picks 256 columns (boundaries) of problem blockIdx.x.  Dynamic
+// LDS: the symbol counters hist[x][thread] (sigma x 256) and the sigma x
+// sigma scores, sized by the alphabet so that more workgroups share a CU.
 __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict__ probs, PdpArrays A,
                                                        const int32_t* __restrict__ subst, uint32_t sigma) {
-  __shared__ uint32_t hist[FAMSA_LCS_MAX_ALPHABET][256];
-  __shared__ int32_t S[FAMSA_LCS_MAX_ALPHABET * FAMSA_LCS_MAX_ALPHABET];
+  extern __shared__ uint32_t pdp_cols_lds[];
+  uint32_t (*hist)[256] = reinterpret_cast<uint32_t (*)[256]>(pdp_cols_lds);
+  int32_t* S = reinterpret_cast<int32_t*>(pdp_cols_lds + sigma * 256u);
   const PdpProb P = probs[blockIdx.x];
   const uint32_t tid = threadIdx.x;
   const uint32_t j = blockIdx.y * 256u + tid;  // column j (0-based) and boundary p = j
@@ -796,8 +799,8 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   hipLaunchKernelGGL(pdp_rows_kernel, dim3(nprob, std::min(64u, (kmax + kRowsPerBlock - 1) / kRowsPerBlock)),
                      dim3(256), 0, st, dprobs, A);
   FAMSA_HIP(hipGetLastError());
-  hipLaunchKernelGGL(pdp_cols_kernel, dim3(nprob, nmax / 256 + 1), dim3(256), 0, st, dprobs, A,
-                     reinterpret_cast<const int32_t*>(D + b_subst), sigma);
+  hipLaunchKernelGGL(pdp_cols_kernel, dim3(nprob, nmax / 256 + 1), dim3(256), 4ull * sigma * (256 + sigma), st,
+                     dprobs, A, reinterpret_cast<const int32_t*>(D + b_subst), sigma);
   FAMSA_HIP(hipGetLastError());
   FAMSA_HIP(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL(pdp_dp_kernel, dim3(nprob), dim3(64 * waves), lds_dyn, st, dprobs, A, sigma);
