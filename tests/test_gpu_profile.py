@@ -108,6 +108,11 @@ def test_wide_values_and_mixed_batches():
     wide = [inputs.profile_problem(int(rng.integers(550, 700)), int(rng.integers(550, 700)), int(rng.integers(20, 40)),
                                    rng) for _ in range(2)]
     check_batch(wide + probs[:2], S, costs)
+    # int32 values with costs too large for 16 bits (K max|S| >= 2^15): the
+    # cost table stays int32 in LDS
+    mid = [inputs.profile_problem(int(rng.integers(60, 150)), int(rng.integers(60, 150)), int(rng.integers(40, 60)),
+                                  rng) for _ in range(4)]
+    check_batch(mid, S, (700, 150, 900, 200))
     # one row and at most 40 columns and residues: below 2^28 even at these costs
     small = [inputs.profile_problem(int(rng.integers(1, 40)), int(rng.integers(1, 40)), 1, rng) for _ in range(6)]
     mixed = [p for pair in zip(probs, small) for p in pair]
