@@ -729,6 +729,16 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
     if (d.lds) lds_dyn = std::max(lds_dyn, need);
     waves = std::max(waves, pdp_waves(d.m, d.n));
   }
+  // With four problems or more per CU the GPU is full of problems, and more
+  // than four waves per problem only add contention (measured on a level of
+  // 2,048 problems of widths 50..500: 0.51 ms with four, 0.54 ms with up to
+  // sixteen); with fewer, the largest problem's chain bounds the level, and
+  // more waves shorten it (its 512 largest problems: 0.41 ms with up to
+  // sixteen, 0.47 ms with four; one problem of 555 x 499: 0.39 ms with eight
+  // waves, 0.46 ms with four).
+  int cus = 0;
+  FAMSA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  if (nprob >= 4u * (uint32_t)std::max(cus, 1)) waves = std::min(waves, 4u);
   if (lds_dyn > 65536)
     FAMSA_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&pdp_dp_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_dyn));
