@@ -7,7 +7,7 @@
 // A batch holds independent problems (the alignments of one level of the
 // guide tree).  Per problem, from the profile's K gapped rows of width n:
 //   pdp_rows_kernel -- a wave per row: the columns of its first and last
-//                      residue (ballots over 64 columns at a time);
+//                      residue (ballots over 256 columns at a time);
 //   pdp_cols_kernel -- a thread per column j: the profile's per-column
 //                      symbol counters (LDS histogram over the rows), the
 //                      column-to-symbol cost table cost[a][j] = sum_x
@@ -17,7 +17,8 @@
 //                      there, from the counts of rows in each of the four
 //                      situations (terminal or inside, next to a gap or
 //                      opening one);
-//   pdp_dp_kernel   -- a workgroup of up to sixteen waves per problem: the
+//   pdp_dp_kernel   -- a workgroup of up to sixteen waves per problem (four
+//                      on levels of four problems or more per CU): the
 //                      three-state DP
 //                        M(i,j) = best(i-1,j-1) + cost[a_i][j]
 //                        D(i,j) = max(M - o w_j, I - o w_j, D - e w_j)(i,j-1)
@@ -30,8 +31,8 @@
 //                      one byte; consecutive strips run on different waves,
 //                      each a fixed number of steps behind the strip above,
 //                      in phases separated by barriers; then the alignment is
-//                      traced back from (m, n), staging the choices in LDS
-//                      4 KB at a time.
+//                      traced back from (m, n) by one wave, staging the
+//                      choices in LDS 4 KB at a time.
 // The DP reads the per-column records, the cost table and the edge rows from
 // LDS when the problem's share fits (it is copied in first), else from
 // global memory.  Ties take the first maximum in the order written (M, D, I),
