@@ -118,3 +118,17 @@ def test_wide_values_and_mixed_batches():
     mixed = [p for pair in zip(probs, small) for p in pair]
     check_batch(mixed, inputs.synthetic_subst(20, 6), (9, 2, 12, 3))
     check_batch(mixed, S, costs)
+
+
+def test_large_level_waves_capped():
+    # a level of 1,100 problems (four or more per CU on a 256-CU GPU: at
+    # most four waves per problem), a few of them wide enough for ten strips
+    # and more strips than waves, so each wave takes several strips in turn
+    rng = np.random.default_rng(71)
+    S = inputs.synthetic_subst(20, 7)
+    costs = OP.scaled_gap_costs(2000, (9, 2, 12, 3))
+    probs = [inputs.profile_problem(int(rng.integers(5, 120)), int(rng.integers(5, 120)), int(rng.integers(1, 20)), rng)
+             for _ in range(1094)]
+    probs += [inputs.profile_problem(int(rng.integers(580, 700)), int(rng.integers(500, 640)), int(rng.integers(2, 12)),
+                                     rng) for _ in range(6)]
+    check_batch(probs, S, costs)
