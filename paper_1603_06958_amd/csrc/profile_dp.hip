@@ -95,6 +95,7 @@ struct PdpArrays {
   int64_t* score;
   uint32_t* nops;
   int64_t To, Te, Go, Ge;  // gap costs: terminal open / extend, inside open / extend
+  uint32_t tb_cap;         // bytes of dynamic LDS every DP workgroup has (its trace-back gathers ops there)
 };
 
 template <typename T>
@@ -512,6 +513,11 @@ __device__ PdpView<T, C> pdp_stage(const PdpProb& P, const PdpArrays& A, char* l
   return PdpView<T, C>{rec, cost, edge};
 }
 
+// A fence on LDS accesses alone: it orders them for the compiler and waits
+// for no global access in flight.
+constexpr uint64_t kTbMinLds = 4096;  // walks of up to 4096 ops stay in LDS
+__device__ inline void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local"); }
+
 __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* __restrict__ probs, PdpArrays A,
                                                                  uint32_t sigma) {
   extern __shared__ uint4 pdp_lds4[];
@@ -550,16 +556,134 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
   if (wave != 0) return;  // wave 0 traces back alone
   const int64_t fM = s_fin[0], fD = s_fin[1], fI = s_fin[2];
   int64_t best;
-  int st = argmax3(fM, fD, fI, &best);
-  // trace back: every lane walks the same path (uniform control flow); the
-  // choice bytes come through a 4 KB LDS window; lane 0 writes the alignment
+  // Trace back, by wave 0 alone; every walk variable is wave-uniform (it
+  // runs on the scalar unit). The choice bytes come through a 4 KB LDS
+  // window, and the window the walk is expected to need next is loaded into
+  // registers while it walks the current one. Inside a strip the walk goes
+  // through a table: lane (a, b) takes the cell a rows up and b columns
+  // left of the walk's cell, and decodes for each state arriving there the
+  // next state and the lane the next step reads, so that a step is one
+  // cross-lane read. Steps the table does not cover (edges of the 8 x 8
+  // block, of a strip or of the window, row 0, column 0) read the window
+  // byte by byte. Ops are gathered in one register (a lane per op), then in
+  // the dynamic LDS, which the DP no longer needs, and written out reversed
+  // at the end; a walk longer than that buffer puts the rest in the output
+  // and reverses it there.
+  int st = __builtin_amdgcn_readfirstlane(argmax3(fM, fD, fI, &best));
   uint8_t* ops = A.ops + P.ops;
-  uint32_t i = m, j = n, k = 0;
-  int win = -2;        // window's region: -1 row 0, s >= 0 strip s
-  uint64_t wlo = 0;    // window's first byte in its region
+  uint8_t* ops_lds = reinterpret_cast<uint8_t*>(pdp_lds4);
+  const uint32_t cap = A.tb_cap;
+  uint32_t i = m, j = n;
+  uint32_t k0 = 0, kk = 0;  // ops stored, ops in acc
+  int acc = 0;              // lane l: op k0 + l
+  int win = -2;             // window in LDS: region (-1 row 0, s >= 0 strip s)
+  uint32_t wlo = 0;         // and its first byte in the region (a strip is under 2^22 bytes)
+  int pwin = -2;            // window in p0..p3
+  uint32_t plo = 0;
+  uint4 p0 = {}, p1 = {}, p2 = {}, p3 = {};
+  auto fetch = [&](int region, uint32_t lo) {
+    const uint8_t* base = region < 0 ? dir : strips + (uint64_t)region * pdp_strip_bytes(n);
+    const uint64_t size = region < 0 ? pdp_row0_bytes(n) : pdp_strip_bytes(n);
+    // lanes past the region's end load its first bytes (never read): no
+    // divergent branch, so the window's bounds stay in scalar registers
+    const uint64_t off = lo + (uint64_t)lane * 64;
+    const uint4* src = reinterpret_cast<const uint4*>(base + (off < size ? off : 0));
+    p0 = src[0];
+    p1 = src[1];
+    p2 = src[2];
+    p3 = src[3];
+  };
+  // make the LDS window hold byte idx of region, the byte of cell (ci, cj)
+  auto window = [&](int region, uint32_t idx, uint32_t ci, uint32_t cj) {
+    if (region == win && idx >= wlo && idx < wlo + 4096) return;
+    if (region != pwin || idx < plo || idx >= plo + 4096) {  // not the window loaded ahead
+      pwin = region;
+      plo = idx >= 4032 ? ((idx - 4032) & ~63u) : 0;
+      fetch(pwin, plo);
+    }
+    lds_fence();  // the old window's reads are done
+    stage4[lane * 4 + 0] = p0;
+    stage4[lane * 4 + 1] = p1;
+    stage4[lane * 4 + 2] = p2;
+    stage4[lane * 4 + 3] = p3;
+    lds_fence();
+    win = pwin;
+    wlo = plo;
+    // load ahead: the next lower window of this region, or, if the walk is
+    // expected to leave the region within this window (a diagonal walk from
+    // row r of a strip leaves it near diagonal cj - r), the next region's
+    // window around where it would enter
+    const uint32_t down = wlo > 3968 ? wlo - 3968 : 0;  // overlaps this window by two diagonals
+    if (win < 0) {
+      pwin = wlo > 0 ? -1 : -2;
+      plo = down;
+    } else {
+      const uint32_t r = (ci - 1) & 63u;
+      if (wlo > 0 && (cj < r || cj - r < (wlo >> 6))) {
+        plo = down;
+      } else if (win > 0) {  // entries on row 63 of strip win - 1 at columns cj - 63 .. cj
+        pwin = win - 1;
+        plo = cj * 64;
+      } else {
+        pwin = -1;
+        plo = cj >= 4032 ? ((cj - 4032) & ~63u) : 0;
+      }
+    }
+    if (pwin != -2) fetch(pwin, plo);
+  };
+  auto flush = [&]() {
+    const uint32_t x = k0 + lane;
+    if (lane < kk && x < cap) ops_lds[x] = (uint8_t)acc;
+    if (lane < kk && x >= cap) ops[x] = (uint8_t)acc;
+    k0 += kk;
+    kk = 0;
+  };
+  auto record = [&](uint32_t op) {  // lane kk of acc takes op
+    acc = lane == kk ? (int)op : acc;
+    ++kk;
+  };
+  const uint32_t ta = lane >> 3, tb = lane & 7u, tdl = ta * 65 + tb * 64;  // this lane's cell in the table
   while (i > 0 || j > 0) {
-    // the byte this step needs: the current cell for D and I, the diagonal
-    // cell for M (after the move)
+    if (kk > 48) flush();  // room for the 14 steps at most that one table takes
+    if (i > 0 && j > 0) {
+      const uint32_t r = (i - 1) & 63u;
+      const uint32_t idx = (j + r) * 64 + r;
+      window((int)((i - 1) >> 6), idx, i, j);
+      const uint32_t o = idx - wlo;
+      // one 10-bit field per arriving state: the next state times 10 and
+      // the step to the lane the next step reads; 31 in the low five bits:
+      // leave the table
+      const bool cell = ta <= r && tb < j && tdl <= o;  // the cell is in this strip, past column 0 and in the window
+      const uint32_t byte = stage[cell ? o - tdl : 0];
+      uint32_t T = 0;
+#pragma unroll
+      for (uint32_t s = 0; s < 3; ++s) {
+        const uint32_t c = (byte >> (2 * s)) & 3u;
+        const uint32_t nx = s == 1 ? (c == 1 ? 2u : (c == 2 ? 1u : c)) : c;
+        const uint32_t na = ta + (s == 2) + (nx == 0), nb = tb + (s == 1) + (nx == 0);
+        const uint32_t f = !cell || nx > 2 || na > 7 || nb > 7 ? 1023u : (10 * nx) | ((na * 8 + nb - lane) << 5);
+        T |= f << (10 * s);
+      }
+      uint32_t sh = 10u * (uint32_t)st;
+      uint32_t Lr = st == 0 ? 9u : 0u;  // the lane this step reads: the cell diagonal to the walk's for M
+      const uint32_t k_in = kk;
+      for (;;) {
+        const uint32_t f = ((uint32_t)__builtin_amdgcn_readlane((int)T, (int)Lr) >> sh) & 1023u;
+        if ((f & 31u) == 31u) break;
+        record(sh >> 3);  // the state's number (0, 10, 20 -> 0, 1, 2)
+        Lr += f >> 5;
+        sh = f & 31u;
+      }
+      if (kk != k_in) {
+        st = (int)(sh >> 3);
+        const uint32_t Lc = st == 0 ? Lr - 9 : Lr;
+        i -= Lc >> 3;
+        j -= Lc & 7u;
+        continue;
+      }
+    }
+    // one step outside the table: the byte this step needs is the walk's
+    // cell for D and I, the diagonal cell for M (after the move)
     uint32_t ci = i, cj = j;
     if (st == 0) {
       if (i == 0 || j == 0) break;  // cannot happen for a consistent matrix
@@ -570,25 +694,11 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
     } else if (i == 0) {
       break;
     }
-    if (lane == 0) ops[k] = (uint8_t)st;
-    ++k;
+    record((uint32_t)st);
     const int region = ci == 0 ? -1 : (int)((ci - 1) >> 6);
-    const uint64_t idx = ci == 0 ? cj : (uint64_t)(cj + ((ci - 1) & 63u)) * 64 + ((ci - 1) & 63u);
-    if (region != win || idx < wlo || idx >= wlo + 4096) {
-      const uint8_t* base = region < 0 ? dir : strips + (uint64_t)region * pdp_strip_bytes(n);
-      const uint64_t size = region < 0 ? pdp_row0_bytes(n) : pdp_strip_bytes(n);
-      win = region;
-      wlo = idx >= 4032 ? ((idx - 4032) & ~(uint64_t)63) : 0;
-      const uint64_t off = wlo + (uint64_t)lane * 64;
-      __syncthreads();  // the previous window's reads are done (wave 0 is the only wave left)
-      if (off < size) {
-        const uint4* src = reinterpret_cast<const uint4*>(base + off);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) stage4[lane * 4 + c] = src[c];
-      }
-      __syncthreads();
-    }
-    const uint32_t byte = stage[idx - wlo];
+    const uint32_t idx = ci == 0 ? cj : (cj + ((ci - 1) & 63u)) * 64 + ((ci - 1) & 63u);
+    window(region, idx, ci, cj);
+    const uint32_t byte = __builtin_amdgcn_readfirstlane(stage[idx - wlo]);
     if (st == 0) {
       i = ci;
       j = cj;
@@ -603,12 +713,20 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
       st = s == 0 ? 0 : (s == 1 ? 1 : 2);
     }
   }
-  __threadfence_block();
-  __syncthreads();
-  for (uint32_t x = lane; x < k / 2; x += 64) {  // ops were written from the last column back
-    const uint8_t u = ops[x], v = ops[k - 1 - x];
-    ops[x] = v;
-    ops[k - 1 - x] = u;
+  flush();
+  const uint32_t k = k0;
+  lds_fence();
+  if (k <= cap) {  // ops were gathered from the last column back
+    for (uint32_t x = lane; x < k; x += 64) ops[x] = ops_lds[k - 1 - x];
+  } else {
+    for (uint32_t x = lane; x < cap; x += 64) ops[x] = ops_lds[x];
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t x = lane; x < k / 2; x += 64) {
+      const uint8_t u = ops[x], v = ops[k - 1 - x];
+      ops[x] = v;
+      ops[k - 1 - x] = u;
+    }
   }
   if (lane == 0) {
     A.score[P.idx] = best;
@@ -740,6 +858,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   int cus = 0;
   FAMSA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   if (nprob >= 4u * (uint32_t)std::max(cus, 1)) waves = std::min(waves, 4u);
+  lds_dyn = std::max<uint64_t>(lds_dyn, kTbMinLds);  // the trace-back's ops buffer
   if (lds_dyn > 65536)
     FAMSA_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&pdp_dp_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_dyn));
@@ -803,6 +922,7 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   A.Te = gap_costs[1];
   A.Go = gap_costs[2];
   A.Ge = gap_costs[3];
+  A.tb_cap = (uint32_t)lds_dyn;
   const PdpProb* dprobs = reinterpret_cast<const PdpProb*>(D + b_probs);
   hipEvent_t ev[2];
   FAMSA_HIP(hipEventCreate(&ev[0]));
