@@ -667,12 +667,12 @@ __global__ __launch_bounds__(64 * kPdpWaves) void pdp_dp_kernel(const PdpProb* _
       uint32_t sh = 10u * (uint32_t)st;
       uint32_t Lr = st == 0 ? 9u : 0u;  // the lane this step reads: the cell diagonal to the walk's for M
       const uint32_t k_in = kk;
-      for (;;) {
-        const uint32_t f = ((uint32_t)__builtin_amdgcn_readlane((int)T, (int)Lr) >> sh) & 1023u;
-        if ((f & 31u) == 31u) break;
-        record(sh >> 3);  // the state's number (0, 10, 20 -> 0, 1, 2)
+      uint32_t f = ((uint32_t)__builtin_amdgcn_readlane((int)T, (int)Lr) >> sh) & 1023u;
+      while ((f & 31u) != 31u) {  // one exit: the loop stays a plain scalar loop
+        record(sh >> 3);          // the state's number (0, 10, 20 -> 0, 1, 2)
         Lr += f >> 5;
         sh = f & 31u;
+        f = ((uint32_t)__builtin_amdgcn_readlane((int)T, (int)Lr) >> sh) & 1023u;
       }
       if (kk != k_in) {
         st = (int)(sh >> 3);
@@ -949,6 +949,8 @@ extern "C" int famsa_profile_align(uint32_t nprob, const uint8_t* seqs, const ui
   (void)hipEventDestroy(ev[1]);
   for (uint32_t p = 0; p < nprob; ++p) {
     if (nops[p] == 0xFFFFFFFFu) return set_error(FAMSA_LCS_EDEVICE, "problem %u: trace-back stopped early", p);
+    if ((uint64_t)nops[p] > (uint64_t)pr[p].m + pr[p].n)  // an alignment has at most m + n ops
+      return set_error(FAMSA_LCS_EDEVICE, "problem %u: %u ops from the device", p, nops[p]);
     memcpy(ops + ops_off[p], hops.data() + pr[p].ops, nops[p]);
   }
   return 0;
