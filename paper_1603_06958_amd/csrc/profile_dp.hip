@@ -31,8 +31,10 @@
 //                      one byte; consecutive strips run on different waves,
 //                      each a fixed number of steps behind the strip above,
 //                      in phases separated by barriers; then the alignment is
-//                      traced back from (m, n) by one wave, staging the
-//                      choices in LDS 4 KB at a time.
+//                      traced back from (m, n) by one wave, the choices
+//                      staged in LDS 4 KB at a time and decoded, an 8 x 8
+//                      block of cells at a time, into a per-lane table of
+//                      next states (a step is one cross-lane read).
 // The DP reads the per-column records, the cost table and the edge rows from
 // LDS when the problem's share fits (it is copied in first), else from
 // global memory.  Ties take the first maximum in the order written (M, D, I),
