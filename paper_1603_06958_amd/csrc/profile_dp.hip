@@ -165,28 +165,33 @@ __global__ __launch_bounds__(256) void pdp_cols_kernel(const PdpProb* __restrict
   for (uint32_t x = 0; x < sigma; ++x) hist[x][tid] = 0;
   __syncthreads();
   if (j > P.n) return;
-  const uint8_t* rows = A.rows + P.rows;
+  // a problem without columns reads the rows part's first byte (always
+  // allocated) and uses none of it
+  const uint8_t* rows = P.n ? A.rows + P.rows : A.rows;
+  const uint32_t jr = P.n ? std::min(j, P.n - 1) : 0, jl = j >= 1 ? j - 1 : 0;  // in-bounds columns
   uint32_t cTA = 0, cTO = 0, cIA = 0, cIO = 0;  // boundary situations: terminal/inside x next to a gap/opening
-  // eight rows at a time, their loads issued together
+  // eight rows at a time; every load is unconditional (rows past K read row
+  // K - 1), so that the eight rows' loads are in flight together
   constexpr uint32_t kU = 8;
   for (uint32_t s0 = 0; s0 < P.K; s0 += kU) {
     uint32_t xr[kU], xl[kU];
     int32_t fr[kU], lr[kU];
 #pragma unroll
     for (uint32_t u = 0; u < kU; ++u) {
-      const uint32_t s = s0 + u;
-      const bool ok = s < P.K;
+      const uint32_t s = std::min(s0 + u, P.K - 1);
       const uint8_t* row = rows + (uint64_t)s * P.n;
-      xr[u] = ok && j < P.n ? row[j] : kGap;
-      xl[u] = ok && j >= 1 ? row[j - 1] : 0u;
-      fr[u] = ok ? A.first[P.rowx + s] : 0;
-      lr[u] = ok ? A.last[P.rowx + s] : 0;
+      const uint32_t br = row[jr], bl = row[jl];
+      xr[u] = j < P.n ? br : kGap;
+      xl[u] = j >= 1 ? bl : 0u;
+      fr[u] = A.first[P.rowx + s];
+      lr[u] = A.last[P.rowx + s];
     }
 #pragma unroll
     for (uint32_t u = 0; u < kU; ++u) {
       if (s0 + u >= P.K) break;
       const uint32_t x = xr[u];
-      if (x != kGap) ++hist[x][tid];
+      if (x != kGap)  // an LDS add whose result is not read: no wait on it
+        __hip_atomic_fetch_add(&hist[x][tid], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       const bool gap_right = j < P.n && x == kGap;
       const bool gap_left = j >= 1 && xl[u] == kGap;
       const bool inside = fr[u] < (int32_t)j && lr[u] >= (int32_t)j;  // residues on both sides of the boundary
