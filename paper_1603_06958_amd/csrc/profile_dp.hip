@@ -129,7 +129,8 @@ __global__ __launch_bounds__(256) void pdp_rows_kernel(const PdpProb* __restrict
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t c = c0 + 64u * u + lane;
-          x[u] = c < P.n ? row[c] : kGap;
+          const uint32_t b = row[std::min(c, P.n - 1)];  // unconditional, so the four loads are in flight together
+          x[u] = c < P.n ? b : kGap;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
